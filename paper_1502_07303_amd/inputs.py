@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs for the Eikonal workloads.
+
+This module only builds inputs.  It holds none of the solver's arithmetic, and
+both the product path and the CPU oracle's tests take their inputs from it.
+
+All grids are node grids on the unit cube: ``n`` points per axis, spacing
+``h = 1 / (n - 1)``, point ``(i0, i1, i2)`` at ``(i0 h, i1 h, i2 h)``.  Arrays
+are C-contiguous with axis 2 fastest, so the linear index is
+``(i0 * n1 + i1) * n2 + i2``.
+
+The workloads mirror the paper's test problems (Sec. 5.1): analytic
+interfaces and point sources with prescribed speed functions.  The paper
+publishes no dataset, so nothing here stands in for external data.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+
+@dataclasses.dataclass
+class Workload:
+    """One solve: speed field, seeds (linear index + value), band width."""
+    name: str
+    F: torch.Tensor            # (n0, n1, n2), float32 or float64
+    h: float
+    seed_idx: torch.Tensor     # int64, on the same device as F
+    seed_val: torch.Tensor     # float64
+    width: float = math.inf
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def shape(self):
+        return tuple(self.F.shape)
+
+    def to(self, device) -> "Workload":
+        return dataclasses.replace(self, F=self.F.to(device), seed_idx=self.seed_idx.to(device),
+                                   seed_val=self.seed_val.to(device))
+
+    def numpy(self):
+        """(F, seed_idx, seed_val) as host numpy arrays."""
+        return (self.F.detach().cpu().numpy(), self.seed_idx.detach().cpu().numpy(),
+                self.seed_val.detach().cpu().numpy())
+
+
+def linear_index(shape, i0, i1, i2):
+    n0, n1, n2 = shape
+    return (np.asarray(i0, dtype=np.int64) * n1 + np.asarray(i1, dtype=np.int64)) * n2 + np.asarray(i2, dtype=np.int64)
+
+
+def point_source(n: int = 64, speed: float = 1.0, dtype=torch.float64, device="cpu",
+                 width: float = math.inf, center: Optional[tuple] = None) -> Workload:
+    """Uniform speed, one source with T = 0 at the centre point ``n // 2`` per axis
+    (paper case 3, Eq. 13, on a node grid)."""
+    c = center if center is not None else (n // 2, n // 2, n // 2)
+    F = torch.full((n, n, n), float(speed), dtype=dtype, device=device)
+    idx = torch.tensor([int(linear_index((n, n, n), *c))], dtype=torch.int64, device=device)
+    val = torch.zeros(1, dtype=torch.float64, device=device)
+    return Workload(f"point_source_{n}", F, 1.0 / (n - 1), idx, val, width, {"center": c})
+
+
+def spheres(n: int = 256, n_spheres: int = 8, seed: int = 0, width: float = 0.1,
+            device="cpu") -> Workload:
+    """Signed-distance reinitialisation of a union of spheres (cf. case 1).
+
+    Centres ~ U[0.2, 0.8]^3 and radii ~ U[0.05, 0.2] from
+    ``numpy.random.default_rng(seed)``; phi(x) = min_k (|x - c_k| - r_k),
+    negative inside.  Seeds are the points adjacent to the interface: phi = 0,
+    or a 6-neighbour with the opposite sign (negative means phi < 0).  Each seed
+    keeps its own phi value.  F = 1 in FP64; both sides march out to |T| <= width.
+    """
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.2, 0.8, size=(n_spheres, 3))
+    radii = rng.uniform(0.05, 0.2, size=n_spheres)
+    h = 1.0 / (n - 1)
+    x = np.arange(n, dtype=np.float64) * h
+    phi = np.full((n, n, n), np.inf)
+    for c, r in zip(centres, radii):
+        d = np.sqrt((x[:, None, None] - c[0]) ** 2 + (x[None, :, None] - c[1]) ** 2
+                    + (x[None, None, :] - c[2]) ** 2) - r
+        np.minimum(phi, d, out=phi)
+    neg = phi < 0
+    adj = phi == 0
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax] = slice(0, n - 1)
+        hi[ax] = slice(1, n)
+        flip = neg[tuple(lo)] != neg[tuple(hi)]
+        adj[tuple(lo)] |= flip
+        adj[tuple(hi)] |= flip
+    idx = np.flatnonzero(adj.reshape(-1)).astype(np.int64)
+    val = phi.reshape(-1)[idx].astype(np.float64)
+    F = torch.ones((n, n, n), dtype=torch.float64, device=device)
+    return Workload(f"spheres_{n}", F, h, torch.from_numpy(idx).to(device),
+                    torch.from_numpy(val).to(device), width,
+                    {"seed": seed, "centres": centres.tolist(), "radii": radii.tolist()})
+
+
+def gaussian_field(n: int, seed: int, corr_len: float = 0.05, device="cpu",
+                   shape: Optional[tuple] = None) -> torch.Tensor:
+    """Periodic Gaussian random field with unit variance and correlation
+    exp(-r^2 / (2 l^2)), l = ``corr_len`` in unit-cube lengths (grid spacing
+    1/(n-1)).  White noise from a seeded torch generator on ``device`` is
+    filtered in Fourier space by exp(-|k|^2 l^2 / 4), then normalised."""
+    shape = shape or (n, n, n)
+    h = 1.0 / (n - 1)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    w = torch.randn(shape, generator=gen, device=device, dtype=torch.float32)
+    W = torch.fft.rfftn(w)
+    del w
+    k = [2 * math.pi * torch.fft.fftfreq(m, d=h, device=device) for m in shape[:2]]
+    k.append(2 * math.pi * torch.fft.rfftfreq(shape[2], d=h, device=device))
+    a = [torch.exp(-(kk ** 2) * corr_len ** 2 / 4).to(torch.float32) for kk in k]
+    W *= a[0][:, None, None]
+    W *= a[1][None, :, None]
+    W *= a[2][None, None, :]
+    g = torch.fft.irfftn(W, s=shape)
+    del W
+    g -= g.mean()
+    g /= g.std()
+    return g
+
+
+def random_speed(n: int = 1024, n_sources: int = 4, seed: int = 0, corr_len: float = 0.05,
+                 log_std: float = 0.5, clip=(0.25, 4.0), device="cpu",
+                 width: float = math.inf) -> Workload:
+    """Speed F = clip(exp(log_std * g), 0.25, 4) stored as FP32, g a seeded
+    Gaussian field (correlation length 0.05), and ``n_sources`` distinct point
+    sources with T = 0 at uniformly drawn grid points (cf. cases 4-5)."""
+    g = gaussian_field(n, seed, corr_len, device=device)
+    F = torch.clamp(torch.exp(log_std * g), clip[0], clip[1]).to(torch.float32).contiguous()
+    del g
+    rng = np.random.default_rng(seed + 7919)
+    pts = set()
+    while len(pts) < n_sources:
+        pts.add(tuple(int(v) for v in rng.integers(0, n, size=3)))
+    pts = sorted(pts)
+    idx = np.array([linear_index((n, n, n), *p) for p in pts], dtype=np.int64)
+    return Workload(f"random_speed_{n}", F, 1.0 / (n - 1), torch.from_numpy(idx).to(device),
+                    torch.zeros(len(idx), dtype=torch.float64, device=device), width,
+                    {"seed": seed, "sources": pts})
+
+
+def random_small(shape=(16, 16, 16), n_sources: int = 2, seed: int = 0, fmin: float = 0.5,
+                 fmax: float = 2.0, dtype=torch.float64, device="cpu",
+                 width: float = math.inf, zero_frac: float = 0.0) -> Workload:
+    """Small grids with i.i.d. uniform speed in [fmin, fmax] (optionally a
+    fraction of impassable F = 0 points) and random point sources; for parity
+    tests over ragged tile counts."""
+    rng = np.random.default_rng(seed)
+    Fn = rng.uniform(fmin, fmax, size=shape)
+    if zero_frac > 0:
+        Fn[rng.random(size=shape) < zero_frac] = 0.0
+    N = int(np.prod(shape))
+    idx = np.sort(rng.choice(N, size=n_sources, replace=False)).astype(np.int64)
+    Fn.reshape(-1)[idx] = np.maximum(Fn.reshape(-1)[idx], fmin)
+    F = torch.from_numpy(Fn).to(dtype).to(device)
+    h = 1.0 / (max(shape) - 1)
+    return Workload(f"random_small_{'x'.join(map(str, shape))}", F, h,
+                    torch.from_numpy(idx).to(device),
+                    torch.zeros(len(idx), dtype=torch.float64, device=device), width,
+                    {"seed": seed})
