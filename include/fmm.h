@@ -1,0 +1,143 @@
+/*
+ * fmm.h -- C ABI of the MI355X restarted narrow-band fast marching solver.
+ *
+ * Solves the Eikonal equation |grad T| F = 1 (Sec. 2.1, Eq. 1) on a uniform
+ * n0 x n1 x n2 node grid with spacing h, using the first-order Godunov upwind
+ * scheme (Eqs. 2-3) and the restarted narrow band method of Yang & Stern
+ * (Sec. 4, Alg. 8-16): tiles of the grid play the paper's subdomains, a
+ * device-wide minimum sets the band bound of each restart (Alg. 16), tiles
+ * march their own narrow band (Alg. 12 with Alg. 10/11) and exchange updated
+ * overlap values through HBM (Alg. 13-15).  All arithmetic is FP64.
+ *
+ * Layout: every grid array is C-contiguous (n0, n1, n2), axis 2 fastest; the
+ * linear index of point (i0, i1, i2) is (i0 * n1 + i1) * n2 + i2.
+ *
+ * Pointers: unless stated otherwise all array arguments are DEVICE pointers
+ * (memory of the current HIP device).  The caller owns every buffer; the
+ * library allocates no device memory.  `stream` is a hipStream_t passed as
+ * void* (NULL = the default stream); calls are asynchronous and ordered on it.
+ *
+ * Threading: calls on different streams with different workspaces are
+ * independent.  Two calls that share a workspace must be ordered by the caller.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes.  Host-detectable argument errors are reported synchronously;
+ * errors found on the device are recorded in the workspace and reported by
+ * fmm_get_stats(). */
+typedef enum {
+    FMM_OK = 0,
+    FMM_EINVAL = -1,  /* bad argument (dims, h, pointer, dtype, option)            */
+    FMM_ENOMEM = -2,  /* workspace smaller than fmm_workspace_bytes()            */
+    FMM_EHIP = -3,    /* a HIP runtime call or kernel launch failed              */
+    FMM_ENOCONV = -4, /* restart limit reached before the band was complete      */
+    FMM_EDEVICE = -5  /* device-detected input error (seeds, speed) or abort     */
+} fmm_status;
+
+/* Storage type of the speed array F (the arithmetic is FP64 either way). */
+typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
+
+/* Option flags. */
+#define FMM_VALIDATE 1u /* check on the device that every F value is finite */
+
+/* Device error bits (fmm_stats.device_error). */
+#define FMM_DERR_SEED_RANGE 1u  /* a seed index outside [0, n0*n1*n2)       */
+#define FMM_DERR_SEED_DUP 2u    /* the same index given twice               */
+#define FMM_DERR_SEED_VALUE 4u  /* a non-finite seed value                  */
+#define FMM_DERR_SPEED 8u       /* non-finite F (only with FMM_VALIDATE)    */
+#define FMM_DERR_NOCONV 16u     /* max_restarts exceeded                    */
+#define FMM_DERR_BARRIER 32u    /* device-wide barrier timed out (abort)    */
+#define FMM_DERR_ROUNDS 64u     /* a tile relaxation exceeded its round cap */
+#define FMM_DERR_LAUNCH 128u    /* the restart driver could not be launched */
+#define FMM_DERR_TIMEOUT 256u   /* the restart driver exceeded opts.time_limit_s */
+
+typedef struct {
+    /* Accept a point iff |T| <= band_width (Alg. 12 pops while |T| <= bound;
+     * the paper's width_band).  INFINITY marches the whole domain. */
+    double band_width;
+    /* Restart stride delta-s in world units (Alg. 16: bound = min(minval +
+     * stride, band_width)).  INFINITY lets every tile march to an empty
+     * band in each restart; a value <= 0 selects 2h, the paper's
+     * recommended stride (Sec. 5.5). */
+    double stride;
+    /* Edge of the cubic grid tiles that play the subdomains: 4, 8 or 16;
+     * 0 selects 8. */
+    int32_t tile_edge;
+    /* Upper bound on restarts (0 = no practical limit); exceeding it stops
+     * the solve with FMM_ENOCONV. */
+    int32_t max_restarts;
+    uint32_t flags; /* FMM_VALIDATE */
+    /* Wall-clock limit of the restart driver in seconds (0 selects 300); a
+     * solve that exceeds it stops with FMM_DERR_TIMEOUT. */
+    uint32_t time_limit_s;
+} fmm_opts;
+
+typedef struct {
+    int64_t n_accepted;     /* accepted non-seed points (|T| <= band_width)       */
+    int64_t n_restarts;     /* entries of the restart loop incl. the exiting one  */
+    int64_t n_reopened;     /* values lowered after they had been accepted        */
+    int64_t n_tile_marches; /* tile activations (Alg. 12 calls on a subdomain)    */
+    int64_t n_solves;       /* local solver evaluations                           */
+    int64_t n_rounds;       /* relaxation rounds summed over tile activations     */
+    double max_abs_T;       /* max |T| over accepted points and seeds             */
+    uint32_t device_error;  /* FMM_DERR_* bits                                     */
+    uint32_t tile_edge;     /* tile edge actually used                             */
+    int64_t n_workgroups;   /* persistent workgroups of the restart driver        */
+} fmm_stats;
+
+/* Fill *opts with the defaults: band_width = INFINITY, stride = 2h (<= 0),
+ * tile_edge = 8, max_restarts = 0, flags = 0, time_limit_s = 0 (300 s). */
+void fmm_default_opts(fmm_opts *opts);
+
+/* Bytes of device workspace fmm_solve() needs for this problem (0 if the
+ * arguments are invalid).  `opts` may be NULL for the defaults. */
+size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, const fmm_opts *opts);
+
+/* Solve.  Inputs (device):
+ *   F         n0*n1*n2 speeds of type F_dtype; F <= 0 (or NaN) marks an
+ *             impassable point that is never solved (cf. case 6, Eq. 16).
+ *   seed_idx  n_seeds distinct linear indices of the points adjacent to the
+ *             interface (Alg. 1/8: the KNOWN_FIX points), may be NULL if
+ *             n_seeds == 0.
+ *   seed_val  their values; the sign selects the side (value < 0 is the
+ *             negative side; +0 and -0 are positive).  Both sides march in
+ *             one pass (Sec. 3); the two sides must be separated by the seeds.
+ * Outputs (device):
+ *   T_out       n0*n1*n2 FP64; accepted points and seeds hold their signed
+ *               values (seeds verbatim), all other points +INFINITY.
+ *   status_out  n0*n1*n2 bytes or NULL: bits 0-1 FAR=0, BAND=1, ACCEPTED=2,
+ *               SEED=3; bit 7 set on the negative side.
+ * Workspace: device memory of at least fmm_workspace_bytes() bytes, 256-byte
+ * aligned; after the call it holds the statistics read by fmm_get_stats().
+ * Returns FMM_OK once all work is enqueued; device-side errors surface in
+ * fmm_get_stats(). */
+int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_dtype F_dtype,
+              const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, const fmm_opts *opts,
+              double *T_out, uint8_t *status_out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Synchronise `stream`, copy the statistics of the last solve that used
+ * `workspace` into *out (host), and return FMM_OK, or FMM_ENOCONV /
+ * FMM_EDEVICE when the device recorded an error. */
+int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream);
+
+/* The local solver on the device (Alg. 11, Eqs. 2-7): out[i] = G(a[3i],
+ * a[3i+1], a[3i+2], r[i]) for i < n, where a holds per-axis upwind values
+ * (+INFINITY for an axis without one) and r = h / F.  All device pointers. */
+int fmm_eval_godunov(const double *a, const double *r, double *out, int64_t n, void *stream);
+
+/* Human-readable text for a return code. */
+const char *fmm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H */

@@ -39,6 +39,8 @@ def _load():
     i64, dbl = ctypes.c_int64, ctypes.c_double
     lib.oracle_godunov.argtypes = [dbl, dbl, dbl, dbl]
     lib.oracle_godunov.restype = dbl
+    lib.oracle_godunov_batch.argtypes = [P, P, P, i64]
+    lib.oracle_godunov_batch.restype = None
     lib.oracle_solve.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, i64, dbl, P, P, P, i64,
                                  ctypes.POINTER(OracleStats)]
     lib.oracle_solve.restype = ctypes.c_int
@@ -55,6 +57,15 @@ def _ptr(a):
 def godunov(a1, a2, a3, r):
     """Local solver G(a1, a2, a3, r) of Alg. 11 (per-axis upwind values, +inf if absent)."""
     return _load().oracle_godunov(float(a1), float(a2), float(a3), float(r))
+
+
+def godunov_batch(a, r):
+    """Vectorised G over an (n, 3) array of upwind values and n values of r."""
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 3)
+    r = np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
+    out = np.empty(r.shape, dtype=np.float64)
+    _load().oracle_godunov_batch(_ptr(a), _ptr(r), _ptr(out), len(r))
+    return out
 
 
 def solve(F, h, seed_idx, seed_val, width=np.inf, record_order=False):

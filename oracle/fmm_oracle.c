@@ -120,6 +120,12 @@ double oracle_godunov(double x, double y, double z, double r)
     return best;
 }
 
+/* Batch form for tests: out[i] = G(a[3i], a[3i+1], a[3i+2], r[i]). */
+void oracle_godunov_batch(const double *a, const double *r, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; i++) out[i] = oracle_godunov(a[3 * i], a[3 * i + 1], a[3 * i + 2], r[i]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Indexed binary min-heap keyed by (|T|, linear index). */
 typedef struct {

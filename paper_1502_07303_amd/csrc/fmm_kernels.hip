@@ -1,0 +1,1014 @@
+// HIP kernels of the restarted narrow-band fast marching method for gfx950.
+//
+// Mapping of the paper's parallel algorithm (Sec. 4) onto one GPU:
+//   subdomain Xi_p with its ghost layer (Sec. 4.1)  -> a cubic grid tile of edge E
+//                                                     held in LDS with a one-point
+//                                                     halo, marched by one wavefront
+//   Initialize_Interface/Heap_Parallel (Alg. 8, 9) -> k_prepare + the first phase
+//                                                     of k_driver
+//   restart loop (Alg. 16)                          -> k_driver: persistent kernel,
+//                                                     device-wide barriers, no host
+//                                                     round trip
+//   AllReduce of the heap-top minima and of the
+//   count of new overlap points (Alg. 16)           -> per-workgroup reduction and
+//                                                     one atomic per workgroup
+//   March_Narrow_Band_Parallel (Alg. 12, 10, 11)    -> tile_march(): label-correcting
+//                                                     relaxation of the tile's band
+//                                                     up to the restart bound
+//   Collect/Exchange/Integrate (Alg. 13-15)         -> owner writes its interior to
+//                                                     HBM and flags the neighbour
+//                                                     tiles whose halo changed; they
+//                                                     re-read the halo in the second
+//                                                     march of the restart
+// Every floating-point expression of the local solver is written out in the
+// order used by the specification of fmm_eval_godunov(); the file is compiled
+// with -ffp-contract=off so no multiply-add is fused.
+#include <math.h>
+
+#include <algorithm>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+#define FMM_INF __builtin_huge_val()
+
+// ---------------------------------------------------------------------------
+// Local solver (Alg. 11 with Eqs. 4-7).  a = per-axis upwind values (+inf when
+// an axis has no upwind neighbour), r = h / F.  With a1 <= a2 <= a3:
+//   u1 = a1 + r
+//   u2 = ((a1 + a2) + sqrt(2 r^2 - (a2 - a1)^2)) * 0.5          causal iff u2 > a2
+//   u3 = (((a1 + a2) + a3) + sqrt(3 r^2 - (((a2-a1)^2 + (a3-a1)^2) + (a3-a2)^2))) / 3
+//                                                                causal iff u3 > a3
+// and G is the smallest causal root (discriminants must be >= 0).  This is the
+// paper's quadratic with the identity (sum a)^2 - k sum a^2 = -sum_{i<j}(a_i-a_j)^2
+// applied, so nothing of size T^2/h^2 cancels.
+__device__ __forceinline__ double godunov(double x, double y, double z, double r)
+{
+    double lo = fmin(x, y), hi = fmax(x, y);
+    double a3 = fmax(hi, z), m = fmin(hi, z);
+    double a1 = fmin(lo, m), a2 = fmax(lo, m);
+    if (!(a1 < FMM_INF)) return FMM_INF;
+    double r2 = r * r;
+    double best = a1 + r;
+    if (a2 < FMM_INF) {
+        double d12 = a2 - a1;
+        double D2 = 2.0 * r2 - d12 * d12;
+        if (D2 >= 0.0) {
+            double u2 = ((a1 + a2) + sqrt(D2)) * 0.5;
+            if (u2 > a2 && u2 < best) best = u2;
+        }
+        if (a3 < FMM_INF) {
+            double d13 = a3 - a1, d23 = a3 - a2;
+            double D3 = 3.0 * r2 - ((d12 * d12 + d13 * d13) + d23 * d23);
+            if (D3 >= 0.0) {
+                double u3 = (((a1 + a2) + a3) + sqrt(D3)) / 3.0;
+                if (u3 > a3 && u3 < best) best = u3;
+            }
+        }
+    }
+    return best;
+}
+
+__global__ void k_eval_godunov(const double *__restrict__ a, const double *__restrict__ r,
+                               double *__restrict__ out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = godunov(a[3 * i], a[3 * i + 1], a[3 * i + 2], r[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Small helpers.
+
+__device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+__device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T> __device__ __forceinline__ T bcast0(T v) { return __shfl(v, 0); }
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t ld_acq(uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_acq64(unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Tile geometry and per-wavefront LDS.
+
+template <int E> struct Geo {
+    static constexpr int D = E + 2;          // tile plus one-point halo per side
+    static constexpr int DV = D * D * D;
+    static constexpr int V = E * E * E;      // interior points
+    static constexpr int K = (V + 63) / 64;  // interior points per lane in a scan
+    static constexpr int FACE = E * E;
+    static constexpr int OX = D * D, OY = D, OZ = 1;
+    static constexpr int LOG = (E == 4) ? 2 : (E == 8) ? 3 : 4;
+    __device__ static constexpr int dom(int i0, int i1, int i2) { return ((i0 + 1) * D + (i1 + 1)) * D + (i2 + 1); }
+    __device__ static constexpr int domp(int p) { return dom(p >> (2 * LOG), (p >> LOG) & (E - 1), p & (E - 1)); }
+};
+
+// Coordinates of halo cell (face f, in-face position u, w): face f = 2*axis +
+// (1 for the + side); the in-face coordinates follow the other two axes in order.
+template <int E> __device__ __forceinline__ void face_cell(int f, int u, int w, int &c0, int &c1, int &c2)
+{
+    const int ax = f >> 1;
+    const int hc = (f & 1) ? E : -1;
+    c0 = ax == 0 ? hc : u;
+    c1 = ax == 0 ? u : (ax == 1 ? hc : w);
+    c2 = ax == 2 ? hc : w;
+}
+
+// The interior cell adjacent to a halo cell of face f.
+template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int &c1, int &c2)
+{
+    const int ax = f >> 1;
+    const int ic = (f & 1) ? E - 1 : 0;
+    if (ax == 0) c0 = ic;
+    else if (ax == 1) c1 = ic;
+    else c2 = ic;
+}
+
+constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
+constexpr int KR = 8;      // candidates per lane held in registers per relaxation step
+constexpr int MAX_ROUNDS = 1 << 16;
+
+enum : uint8_t { FL_SEED = 1, FL_UPD = 2, FL_CHG = 4 };
+enum { MODE_INIT = 0, MODE_M1 = 1, MODE_M2 = 2 };
+
+template <int E, typename FT> struct WaveLds {
+    double T[Geo<E>::DV];                 // domain values (interior + face halos)
+    FT F[Geo<E>::V];                      // interior speeds
+    uint16_t list[2][Geo<E>::V];          // candidate lists (interior indices)
+    alignas(8) uint8_t cf[Geo<E>::V];     // candidate flags (interior indices)
+    uint8_t fl[Geo<E>::DV];               // FL_* per domain cell
+    uint32_t stL[STAGE];                  // staged live-list appends
+    uint32_t stD[STAGE];                  // staged dirty-list appends
+};
+
+template <int NW> struct WgShared {
+    uint32_t cntL[NW], cntD[NW], pend[NW];
+    double gmin0[NW], gmin1[NW];
+    uint32_t baseL, baseD;
+    uint32_t ok;
+};
+
+struct WaveState {
+    uint32_t nL, nD;      // staged entries (wave-uniform)
+    uint32_t pending;     // tiles newly dirtied for the next restart
+    double gmin0, gmin1;  // running min of band minima
+    unsigned long long n_march, n_round;  // wave-uniform counters
+    unsigned long long n_solve, n_reopen;  // per-lane counters
+};
+
+// ---------------------------------------------------------------------------
+// Device-wide barrier for the persistent driver.  All workgroups of the
+// cooperative launch are co-resident.  A bounded wait turns any failure into
+// an abort that every workgroup observes, so the kernel always terminates.
+
+__device__ bool grid_barrier(Ctrl *c, uint32_t &gen, uint32_t nwg, uint32_t *s_ok)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        gen++;
+        uint32_t target = gen * nwg;
+        uint32_t ok = 1;
+        __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long t0 = wall_clock64();
+        while (ld_acq(&c->bar) < target) {
+            if (ld_acq(&c->abort)) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (wall_clock64() - t0 > 2000000000ull) {  // 20 s at the 100 MHz constant clock
+                atomicOr(&c->error_run, ERR_BARRIER);
+                atomicExch(&c->abort, 1u);
+                ok = 0;
+                break;
+            }
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level list staging.
+
+__device__ __forceinline__ void stage_push(uint32_t *st, uint32_t &n, uint32_t v, uint32_t *counter, uint32_t *list)
+{
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) st[n] = v;
+    n++;
+    if (n == STAGE) {
+        wave_sync();
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(counter, (uint32_t)STAGE);
+        base = bcast0(base);
+        list[base + lane] = st[lane];
+        n = 0;
+        wave_sync();
+    }
+}
+
+// Compact the candidate flags cf[0..V) into `out` (ascending interior index),
+// clearing them; returns the count (wave-uniform).
+template <int E, typename FT> __device__ __forceinline__ int compact(WaveLds<E, FT> &L, uint16_t *out)
+{
+    constexpr int K = Geo<E>::K;
+    const int lane = threadIdx.x & 63;
+    uint32_t cnt = 0;
+    if (lane * K < Geo<E>::V) {
+#pragma unroll
+        for (int j = 0; j < K; j++) cnt += L.cf[lane * K + j] != 0;
+    }
+    uint32_t pre = 0, total = 0;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int b = 0; (1 << b) <= K; b++) {
+        unsigned long long m = __ballot((cnt >> b) & 1u);
+        pre += (uint32_t)__popcll(m & lt) << b;
+        total += (uint32_t)__popcll(m) << b;
+    }
+    if (cnt) {
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+            int p = lane * K + j;
+            if (L.cf[p]) {
+                out[pre++] = (uint16_t)p;
+                L.cf[p] = 0;
+            }
+        }
+    }
+    wave_sync();
+    return (int)total;
+}
+
+// Mark the updatable interior neighbours of interior point p (domain cell d).
+template <int E, typename FT> __device__ __forceinline__ void mark_nbrs(WaveLds<E, FT> &L, int p, int d)
+{
+    using G = Geo<E>;
+    if (L.fl[d - G::OX] & FL_UPD) L.cf[p - E * E] = 1;
+    if (L.fl[d + G::OX] & FL_UPD) L.cf[p + E * E] = 1;
+    if (L.fl[d - G::OY] & FL_UPD) L.cf[p - E] = 1;
+    if (L.fl[d + G::OY] & FL_UPD) L.cf[p + E] = 1;
+    if (L.fl[d - G::OZ] & FL_UPD) L.cf[p - 1] = 1;
+    if (L.fl[d + G::OZ] & FL_UPD) L.cf[p + 1] = 1;
+}
+
+// A domain cell is a source of the relaxation when it is a seed, or when its
+// value is finite and within the band bound of its side (the KNOWN-class
+// points of Alg. 11 for this restart).
+__device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd[2])
+{
+    double a = fabs(v);
+    if (!(a < FMM_INF)) return false;
+    if (fl & FL_SEED) return true;
+    return a <= (v < 0.0 ? bnd[0] : bnd[1]);
+}
+
+// Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
+// new signed value if it improves on the current one.
+template <int E, typename FT>
+__device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, double h, const double bnd[2], double &out)
+{
+    using G = Geo<E>;
+    const int d = G::domp(p);
+    const double vp = L.T[d];
+    const double ap = fabs(vp);
+    double am[3], ap3[3];  // per-axis minima for side - and side +
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+        const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
+        double mneg = FMM_INF, mpos = FMM_INF;
+#pragma unroll
+        for (int s = -1; s <= 1; s += 2) {
+            const int dn = d + s * off;
+            const double v = L.T[dn];
+            const double a = fabs(v);
+            if (a < ap && is_source(v, L.fl[dn], bnd)) {
+                if (v < 0.0)
+                    mneg = fmin(mneg, a);
+                else
+                    mpos = fmin(mpos, a);
+            }
+        }
+        am[ax] = mneg;
+        ap3[ax] = mpos;
+    }
+    const double r = h / (double)L.F[p];
+    double best = ap;
+    bool neg = vp < 0.0;
+    bool improved = false;
+    if (fmin(am[0], fmin(am[1], am[2])) < FMM_INF) {
+        double u = godunov(am[0], am[1], am[2], r);
+        if (u < best || (u == best && !neg && best < FMM_INF)) {
+            best = u;
+            neg = true;
+            improved = true;
+        }
+    }
+    if (fmin(ap3[0], fmin(ap3[1], ap3[2])) < FMM_INF) {
+        double u = godunov(ap3[0], ap3[1], ap3[2], r);
+        if (u < best) {
+            best = u;
+            neg = false;
+            improved = true;
+        }
+    }
+    out = neg ? -best : best;
+    return improved;
+}
+
+// ---------------------------------------------------------------------------
+// One activation of a tile by one wavefront: load tile + halo into LDS, relax
+// its band up to the restart bound (Alg. 12 via Alg. 10/11), write back the
+// changed points, flag neighbours whose halo changed (Alg. 13/14), and record
+// the tile's pending band minimum (the heap top of Alg. 16).
+
+template <int E, typename FT>
+__device__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int mode, uint32_t dbits,
+                           const double bnd[2], const double lastb[2], uint32_t epoch, WaveState &ws,
+                           uint32_t *listNext, uint32_t *cntNext, uint32_t *dlist, uint32_t *cntD,
+                           uint32_t *dprod)
+{
+    using G = Geo<E>;
+    constexpr int V = G::V, FACE = G::FACE;
+    const int lane = threadIdx.x & 63;
+    const FT *__restrict__ Fg = (const FT *)P.F;
+    double *__restrict__ Tg = P.T;
+
+    const int32_t tz = (int32_t)(t % (uint32_t)P.t2);
+    const int32_t ty = (int32_t)((t / (uint32_t)P.t2) % (uint32_t)P.t1);
+    const int32_t tx = (int32_t)(t / ((uint32_t)P.t2 * (uint32_t)P.t1));
+    const int64_t o0 = (int64_t)tx * E, o1 = (int64_t)ty * E, o2 = (int64_t)tz * E;
+    const int e0 = (int)min((int64_t)E, P.n0 - o0), e1 = (int)min((int64_t)E, P.n1 - o1),
+              e2 = (int)min((int64_t)E, P.n2 - o2);
+    const int64_t n12 = P.n1 * P.n2;
+    const uint32_t tsx = (uint32_t)P.t1 * (uint32_t)P.t2, tsy = (uint32_t)P.t2;
+    const bool hasSeed = (P.tflags[t] & TF_SEED) != 0;
+    const unsigned long long *mask = P.mask + (size_t)t * P.mask_words;
+
+    // ---- load interior
+    for (int p = lane; p < V; p += 64) {
+        const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
+        const int d = G::dom(i0, i1, i2);
+        double v = FMM_INF;
+        FT f = (FT)0;
+        uint8_t fl = 0;
+        if (i0 < e0 && i1 < e1 && i2 < e2) {
+            const int64_t g = (o0 + i0) * n12 + (o1 + i1) * P.n2 + (o2 + i2);
+            v = Tg[g];
+            f = Fg[g];
+            const bool seed = hasSeed && ((mask[p >> 6] >> (p & 63)) & 1ull);
+            fl = seed ? FL_SEED : ((double)f > 0.0 ? FL_UPD : 0);
+        }
+        L.T[d] = v;
+        L.F[p] = f;
+        L.fl[d] = fl;
+        L.cf[p] = 0;
+    }
+    // ---- load the six face halos (+inf outside the grid)
+    for (int q = lane; q < 6 * FACE; q += 64) {
+        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+        const int ax = f >> 1;
+        const bool plus = f & 1;
+        int c0, c1, c2;
+        face_cell<E>(f, u, w, c0, c1, c2);
+        const int d = G::dom(c0, c1, c2);
+        double v = FMM_INF;
+        uint8_t fl = 0;
+        // in-face extent (ragged tiles) and the halo coordinate inside the grid
+        const int ua = ax == 0 ? e1 : e0, wa = ax == 2 ? e1 : e2;
+        const int64_t gh = ax == 0 ? o0 + c0 : ax == 1 ? o1 + c1 : o2 + c2;
+        const int64_t na = ax == 0 ? P.n0 : ax == 1 ? P.n1 : P.n2;
+        if (u < ua && w < wa && gh >= 0 && gh < na) {
+            const int64_t g = (o0 + c0) * n12 + (o1 + c1) * P.n2 + (o2 + c2);
+            v = Tg[g];
+            const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+            const uint32_t tnb = plus ? t + ts : t - ts;
+            if (P.tflags[tnb] & TF_SEED) {
+                int n0c = c0, n1c = c1, n2c = c2;
+                if (ax == 0) n0c = plus ? 0 : E - 1;
+                else if (ax == 1) n1c = plus ? 0 : E - 1;
+                else n2c = plus ? 0 : E - 1;
+                const int pn = (n0c * E + n1c) * E + n2c;
+                if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
+            }
+        }
+        L.T[d] = v;
+        L.fl[d] = fl;
+    }
+    wave_sync();
+
+    // ---- initial candidates: neighbours of cells that became sources since
+    // this tile's last march (seeds count as new only in the first phase), and
+    // interior cells next to a halo face that changed.
+    const bool init = mode == MODE_INIT;
+    for (int p = lane; p < V; p += 64) {
+        const int d = G::domp(p);
+        const double v = L.T[d];
+        const uint8_t fl = L.fl[d];
+        if (is_source(v, fl, bnd)) {
+            const double a = fabs(v);
+            const bool before = (fl & FL_SEED) ? !init : a <= (v < 0.0 ? lastb[0] : lastb[1]);
+            if (!before) mark_nbrs(L, p, d);
+        }
+    }
+    for (int q = lane; q < 6 * FACE; q += 64) {
+        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+        int c0, c1, c2;
+        face_cell<E>(f, u, w, c0, c1, c2);
+        const int d = G::dom(c0, c1, c2);
+        face_inner<E>(f, c0, c1, c2);
+        const int pi = (c0 * E + c1) * E + c2;
+        const int di = G::dom(c0, c1, c2);
+        if (!(L.fl[di] & FL_UPD)) continue;
+        const double v = L.T[d];
+        const uint8_t fl = L.fl[d];
+        bool mark = (dbits >> f) & 1u;
+        if (!mark && is_source(v, fl, bnd)) {
+            const double a = fabs(v);
+            const bool before = (fl & FL_SEED) ? !init : a <= (v < 0.0 ? lastb[0] : lastb[1]);
+            mark = !before;
+        }
+        if (mark) L.cf[pi] = 1;
+    }
+    wave_sync();
+
+    // ---- relaxation rounds (Jacobi: all evaluations of a round read the
+    // values of the previous round, so the result is independent of lane order)
+    int cur = 0;
+    int n = compact(L, L.list[0]);
+    int rounds = 0;
+    while (n > 0) {
+        if (++rounds > MAX_ROUNDS) {
+            if (lane == 0) atomicOr(&P.ctrl->error_run, ERR_ROUNDS);
+            break;
+        }
+        for (int base = 0; base < n; base += 64 * KR) {
+            double nv[KR];
+            bool ch[KR];
+#pragma unroll
+            for (int j = 0; j < KR; j++) {
+                const int k = base + lane + 64 * j;
+                ch[j] = false;
+                nv[j] = 0.0;
+                if (k < n) {
+                    ch[j] = eval_point(L, (int)L.list[cur][k], P.h, bnd, nv[j]);
+                    ws.n_solve++;
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int j = 0; j < KR; j++) {
+                const int k = base + lane + 64 * j;
+                if (k < n && ch[j]) {
+                    const int p = L.list[cur][k];
+                    const int d = G::domp(p);
+                    const double old = L.T[d];
+                    if (is_source(old, 0, bnd) || fabs(old) <= (old < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
+                    L.T[d] = nv[j];
+                    L.fl[d] |= FL_CHG;
+                    if (is_source(nv[j], 0, bnd)) mark_nbrs(L, p, d);
+                }
+            }
+            wave_sync();
+        }
+        cur ^= 1;
+        n = compact(L, L.list[cur]);
+    }
+    ws.n_round += rounds;
+    ws.n_march++;
+
+    // ---- write back changed interior points; collect changed faces
+    uint32_t fmask = 0;
+    for (int p = lane; p < V; p += 64) {
+        const int d = G::domp(p);
+        if (L.fl[d] & FL_CHG) {
+            const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
+            const int64_t g = (o0 + i0) * n12 + (o1 + i1) * P.n2 + (o2 + i2);
+            Tg[g] = L.T[d];
+            fmask |= (i0 == 0 ? 1u : 0u) | (i0 == E - 1 ? 2u : 0u) | (i1 == 0 ? 4u : 0u) |
+                     (i1 == E - 1 ? 8u : 0u) | (i2 == 0 ? 16u : 0u) | (i2 == E - 1 ? 32u : 0u);
+        }
+    }
+    uint32_t faces = 0;
+#pragma unroll
+    for (int f = 0; f < 6; f++)
+        if (__ballot((fmask >> f) & 1u)) faces |= 1u << f;
+
+    // ---- pending band minimum per side: interior band values above the
+    // bound, and halo values above the bound next to an interior point that
+    // is not yet a source (they become sources of this tile in a later restart)
+    double tm0 = FMM_INF, tm1 = FMM_INF;
+    for (int p = lane; p < V; p += 64) {
+        const int d = G::domp(p);
+        if (!(L.fl[d] & FL_UPD)) continue;
+        const double v = L.T[d];
+        const double a = fabs(v);
+        if (a < FMM_INF) {
+            if (v < 0.0) {
+                if (a > bnd[0]) tm0 = fmin(tm0, a);
+            } else if (a > bnd[1]) {
+                tm1 = fmin(tm1, a);
+            }
+        }
+    }
+    for (int q = lane; q < 6 * FACE; q += 64) {
+        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+        int c0, c1, c2;
+        face_cell<E>(f, u, w, c0, c1, c2);
+        const int d = G::dom(c0, c1, c2);
+        const double v = L.T[d];
+        const double a = fabs(v);
+        if (!(a < FMM_INF) || (L.fl[d] & FL_SEED)) continue;
+        if (a <= (v < 0.0 ? bnd[0] : bnd[1])) continue;
+        face_inner<E>(f, c0, c1, c2);
+        const int di = G::dom(c0, c1, c2);
+        if (!(L.fl[di] & FL_UPD) || is_source(L.T[di], 0, bnd)) continue;
+        if (v < 0.0)
+            tm0 = fmin(tm0, a);
+        else
+            tm1 = fmin(tm1, a);
+    }
+    tm0 = wave_min(tm0);
+    tm1 = wave_min(tm1);
+    if (lane == 0) {
+        TileMeta m;
+        m.tmin[0] = tm0;
+        m.tmin[1] = tm1;
+        m.lastb[0] = bnd[0];
+        m.lastb[1] = bnd[1];
+        P.meta[t] = m;
+    }
+    ws.gmin0 = fmin(ws.gmin0, tm0);
+    ws.gmin1 = fmin(ws.gmin1, tm1);
+
+    // ---- flag neighbours whose halo changed (the overlap exchange)
+    for (int f = 0; f < 6; f++) {
+        if (!((faces >> f) & 1u)) continue;
+        const int ax = f >> 1;
+        const bool plus = f & 1;
+        const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
+        const int32_t tna = ax == 0 ? P.t0 : ax == 1 ? P.t1 : P.t2;
+        if (plus ? tca + 1 >= tna : tca == 0) continue;
+        const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+        const uint32_t u = plus ? t + ts : t - ts;
+        uint32_t old = 0;
+        if (lane == 0) old = atomicOr(&dprod[u], 1u << (f ^ 1));
+        old = bcast0(old);
+        if (old != 0) continue;
+        if (mode == MODE_M1) {
+            stage_push(L.stD, ws.nD, u, cntD, dlist);
+        } else {
+            ws.pending++;
+            uint32_t oe = 0;
+            if (lane == 0) oe = atomicExch(&P.epoch[u], epoch);
+            oe = bcast0(oe);
+            if (oe != epoch) stage_push(L.stL, ws.nL, u, cntNext, listNext);
+        }
+    }
+    // ---- keep the tile in the next restart's list while it has a band
+    if (tm0 < FMM_INF || tm1 < FMM_INF) {
+        uint32_t oe = 0;
+        if (lane == 0) oe = atomicExch(&P.epoch[t], epoch);
+        oe = bcast0(oe);
+        if (oe != epoch) stage_push(L.stL, ws.nL, t, cntNext, listNext);
+    }
+    wave_sync();
+}
+
+// ---------------------------------------------------------------------------
+// Persistent restart driver (Alg. 16).
+
+template <int E, int NW, typename FT>
+__device__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
+                          const uint32_t *items, uint32_t nitems, const double bnd[2], WaveState &ws)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    Ctrl *c = P.ctrl;
+    Slot &cur = c->slot[r % 3];
+    Slot &nxt = c->slot[(r + 1) % 3];
+    uint32_t *listNext = ((r + 1) & 1) ? P.list1 : P.list0;
+    const uint32_t epoch = r + 1;
+    uint32_t *dcons = mode == MODE_M1 ? P.dirty0 : P.dirty1;
+    uint32_t *dprod = mode == MODE_M1 ? P.dirty1 : P.dirty0;
+    const uint32_t gw = blockIdx.x * NW + wid, GW = gridDim.x * NW;
+
+    for (uint32_t i = gw; i < nitems; i += GW) {
+        if (ld_acq(&c->abort)) break;
+        const uint32_t t = items[i];
+        uint32_t dbits = 0;
+        double lastb[2] = {-FMM_INF, -FMM_INF};
+        if (mode != MODE_INIT) {
+            if (lane == 0) dbits = atomicExch(&dcons[t], 0u);
+            dbits = bcast0(dbits);
+            const TileMeta m = P.meta[t];
+            lastb[0] = m.lastb[0];
+            lastb[1] = m.lastb[1];
+            const bool due = dbits != 0 || (m.tmin[0] < FMM_INF && m.tmin[0] <= bnd[0]) ||
+                             (m.tmin[1] < FMM_INF && m.tmin[1] <= bnd[1]);
+            if (!due) {
+                // carried over unchanged to the next restart
+                ws.gmin0 = fmin(ws.gmin0, m.tmin[0]);
+                ws.gmin1 = fmin(ws.gmin1, m.tmin[1]);
+                if (m.tmin[0] < FMM_INF || m.tmin[1] < FMM_INF) {
+                    uint32_t oe = 0;
+                    if (lane == 0) oe = atomicExch(&P.epoch[t], epoch);
+                    oe = bcast0(oe);
+                    if (oe != epoch) stage_push(L.stL, ws.nL, t, &nxt.live_len, listNext);
+                }
+                continue;
+            }
+        }
+        tile_march<E, FT>(P, L, t, mode, dbits, bnd, lastb, epoch, ws, listNext, &nxt.live_len, P.dlist,
+                          &cur.d_len, dprod);
+    }
+
+    // ---- workgroup epilogue: one atomic per list / reduction per workgroup
+    if (lane == 0) {
+        S.cntL[wid] = ws.nL;
+        S.cntD[wid] = ws.nD;
+        S.pend[wid] = ws.pending;
+        S.gmin0[wid] = ws.gmin0;
+        S.gmin1[wid] = ws.gmin1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tl = 0, td = 0, tp = 0;
+        double g0 = FMM_INF, g1 = FMM_INF;
+        for (int w = 0; w < NW; w++) {
+            tl += S.cntL[w];
+            td += S.cntD[w];
+            tp += S.pend[w];
+            g0 = fmin(g0, S.gmin0[w]);
+            g1 = fmin(g1, S.gmin1[w]);
+        }
+        S.baseL = tl ? atomicAdd(&nxt.live_len, tl) : 0u;
+        S.baseD = td ? atomicAdd(&cur.d_len, td) : 0u;
+        if (tp) atomicAdd(&nxt.pending, tp);
+        if (g0 < FMM_INF) atomicMin(&nxt.gmin[0], dbits(g0));
+        if (g1 < FMM_INF) atomicMin(&nxt.gmin[1], dbits(g1));
+    }
+    __syncthreads();
+    uint32_t offL = S.baseL, offD = S.baseD;
+    for (int w = 0; w < wid; w++) {
+        offL += S.cntL[w];
+        offD += S.cntD[w];
+    }
+    for (uint32_t k = lane; k < ws.nL; k += 64) listNext[offL + k] = L.stL[k];
+    for (uint32_t k = lane; k < ws.nD; k += 64) P.dlist[offD + k] = L.stD[k];
+    ws.nL = ws.nD = 0;
+    ws.pending = 0;
+    ws.gmin0 = ws.gmin1 = FMM_INF;
+}
+
+template <int E, int NW, typename FT>
+__global__ void __launch_bounds__(NW * 64) k_driver(Params P)
+{
+    __shared__ WaveLds<E, FT> s_wave[NW];
+    __shared__ WgShared<NW> s_g;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    WaveLds<E, FT> &L = s_wave[wid];
+    Ctrl *c = P.ctrl;
+    const uint32_t nwg = gridDim.x;
+    uint32_t gen = 0;
+    WaveState ws;
+    ws.nL = ws.nD = 0;
+    ws.pending = 0;
+    ws.gmin0 = ws.gmin1 = FMM_INF;
+    ws.n_march = ws.n_round = ws.n_solve = ws.n_reopen = 0;
+
+    const unsigned long long t_start = wall_clock64();
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->nwg = nwg;
+    if (ld_acq(&c->error) == 0) {
+        // Heap initialisation (Alg. 9): only seeds are sources.
+        const double nob[2] = {-1.0, -1.0};
+        run_phase<E, NW, FT>(P, L, s_g, MODE_INIT, 0u, P.list0, ld_acq(&c->slot[0].live_len), nob, ws);
+        if (grid_barrier(c, gen, nwg, &s_g.ok)) {
+            for (uint32_t r = 1;; r++) {
+                Slot &S = c->slot[r % 3];
+                const double g0 = bitsd(ld_acq64(&S.gmin[0])), g1 = bitsd(ld_acq64(&S.gmin[1]));
+                const uint32_t pend = ld_acq(&S.pending);
+                const uint32_t len = ld_acq(&S.live_len);
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    Slot &Z = c->slot[(r + 2) % 3];
+                    Z.gmin[0] = Z.gmin[1] = dbits(FMM_INF);
+                    Z.live_len = Z.pending = Z.d_len = 0;
+                }
+                // Alg. 16 exit test: both sides have no band value within the
+                // width (an empty band reports +inf) and no tile is left dirty.
+                const bool done0 = !(g0 < FMM_INF && g0 <= P.width);
+                const bool done1 = !(g1 < FMM_INF && g1 <= P.width);
+                if (done0 && done1 && pend == 0) {
+                    if (blockIdx.x == 0 && threadIdx.x == 0) c->restarts = r;
+                    break;
+                }
+                if (P.max_restarts > 0 && (int64_t)r > P.max_restarts) {
+                    if (blockIdx.x == 0 && threadIdx.x == 0) {
+                        atomicOr(&c->error_run, ERR_NOCONV);
+                        c->restarts = r;
+                    }
+                    break;
+                }
+                // Safety net: workgroup 0 aborts a solve that exceeds the time
+                // limit; the others leave at their next barrier.
+                if (blockIdx.x == 0 && wall_clock64() - t_start > P.time_limit_ticks) {
+                    if (threadIdx.x == 0) {
+                        atomicOr(&c->error_run, ERR_TIMEOUT);
+                        atomicExch(&c->abort, 1u);
+                        c->restarts = r;
+                    }
+                    break;
+                }
+                // bound = min(minval + stride, width) per side (Alg. 16)
+                const double bnd[2] = {fmin(g0 + P.stride, P.width), fmin(g1 + P.stride, P.width)};
+                run_phase<E, NW, FT>(P, L, s_g, MODE_M1, r, (r & 1) ? P.list1 : P.list0, len, bnd, ws);
+                if (!grid_barrier(c, gen, nwg, &s_g.ok)) break;
+                run_phase<E, NW, FT>(P, L, s_g, MODE_M2, r, P.dlist, ld_acq(&S.d_len), bnd, ws);
+                if (!grid_barrier(c, gen, nwg, &s_g.ok)) break;
+            }
+        }
+    }
+    // ---- statistics
+    const unsigned long long ns = wave_sum(ws.n_solve), nr = wave_sum(ws.n_reopen);
+    if (lane == 0) {
+        atomicAdd(&c->n_march, ws.n_march);
+        atomicAdd(&c->n_round, ws.n_round);
+        atomicAdd(&c->n_solve, ns);
+        atomicAdd(&c->n_reopen, nr);
+    }
+    (void)wid;
+}
+
+// ---------------------------------------------------------------------------
+// Preparation: workspace reset, T = +inf, seeds (Alg. 8), initial tile list.
+
+__global__ void k_init_ws(Params P, int E)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
+        Ctrl *c = P.ctrl;
+        c->bar = 0;
+        c->abort = 0;
+        c->error = 0;
+        c->error_run = 0;
+        c->restarts = 0;
+        c->nwg = 0;
+        c->tile_edge = (uint32_t)E;
+        for (int k = 0; k < 3; k++) {
+            c->slot[k].gmin[0] = c->slot[k].gmin[1] = dbits(FMM_INF);
+            c->slot[k].live_len = c->slot[k].pending = c->slot[k].d_len = 0;
+        }
+        c->n_march = c->n_solve = c->n_round = c->n_reopen = 0;
+        c->n_accepted = 0;
+        c->max_abs_bits = 0;
+    }
+    for (int64_t i = i0; i < (int64_t)P.ntiles; i += stride) {
+        TileMeta m;
+        m.tmin[0] = m.tmin[1] = FMM_INF;
+        m.lastb[0] = m.lastb[1] = -FMM_INF;
+        P.meta[i] = m;
+        P.dirty0[i] = 0;
+        P.dirty1[i] = 0;
+        P.epoch[i] = 0;
+        P.tflags[i] = 0;
+    }
+    const int64_t nm = (int64_t)P.ntiles * P.mask_words;
+    for (int64_t i = i0; i < nm; i += stride) P.mask[i] = 0ull;
+}
+
+__global__ void k_fill_inf(double *__restrict__ T, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) T[i] = FMM_INF;
+}
+
+__device__ __forceinline__ void add_init_tile(const Params &P, uint32_t t)
+{
+    const uint32_t old = atomicOr(&P.tflags[t], (uint32_t)TF_INIT);
+    if (!(old & TF_INIT)) {
+        const uint32_t pos = atomicAdd(&P.ctrl->slot[0].live_len, 1u);
+        P.list0[pos] = t;
+    }
+}
+
+__global__ void k_seeds(Params P, const int64_t *__restrict__ idx, const double *__restrict__ val, int64_t ns, int E)
+{
+    const int64_t N = P.n0 * P.n1 * P.n2;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = idx[k];
+        const double v = val[k];
+        if (g < 0 || g >= N) {
+            atomicOr(&P.ctrl->error, ERR_SEED_RANGE);
+            continue;
+        }
+        if (!(fabs(v) < FMM_INF)) {
+            atomicOr(&P.ctrl->error, ERR_SEED_VALUE);
+            continue;
+        }
+        const int64_t i0 = g / (P.n1 * P.n2), rem = g - i0 * (P.n1 * P.n2);
+        const int64_t i1 = rem / P.n2, i2 = rem - i1 * P.n2;
+        const int64_t c[3] = {i0 / E, i1 / E, i2 / E};
+        const int l[3] = {(int)(i0 - c[0] * E), (int)(i1 - c[1] * E), (int)(i2 - c[2] * E)};
+        const uint32_t ts[3] = {(uint32_t)P.t1 * (uint32_t)P.t2, (uint32_t)P.t2, 1u};
+        const int32_t tn[3] = {P.t0, P.t1, P.t2};
+        const uint32_t t = (uint32_t)((c[0] * P.t1 + c[1]) * P.t2 + c[2]);
+        const int p = (l[0] * E + l[1]) * E + l[2];
+        const unsigned long long bit = 1ull << (p & 63);
+        const unsigned long long old = atomicOr(&P.mask[(size_t)t * P.mask_words + (p >> 6)], bit);
+        if (old & bit) {
+            atomicOr(&P.ctrl->error, ERR_SEED_DUP);
+            continue;
+        }
+        P.T[g] = v;
+        atomicOr(&P.tflags[t], (uint32_t)TF_SEED);
+        add_init_tile(P, t);
+        for (int ax = 0; ax < 3; ax++) {
+            if (l[ax] == 0 && c[ax] > 0) add_init_tile(P, t - ts[ax]);
+            if (l[ax] == E - 1 && c[ax] + 1 < tn[ax]) add_init_tile(P, t + ts[ax]);
+        }
+    }
+}
+
+template <typename FT> __global__ void k_validate(Params P)
+{
+    const int64_t N = P.n0 * P.n1 * P.n2;
+    const FT *F = (const FT *)P.F;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !(fabs((double)F[i]) < FMM_INF);
+    if (bad) atomicOr(&P.ctrl->error, ERR_SPEED);
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: status bytes, +inf for points outside the band, statistics.
+
+__global__ void k_finalize(Params P, uint8_t *__restrict__ status, int E)
+{
+    const int64_t rows = P.n0 * P.n1;
+    const int64_t chunks = (P.n2 + blockDim.x - 1) / blockDim.x;
+    unsigned long long acc = 0;
+    double mx = 0.0;
+    for (int64_t wi = blockIdx.x; wi < rows * chunks; wi += gridDim.x) {
+        const int64_t row = wi / chunks, ch = wi - row * chunks;
+        const int64_t i2 = ch * blockDim.x + threadIdx.x;
+        if (i2 >= P.n2) continue;
+        const int64_t i0 = row / P.n1, i1 = row - i0 * P.n1;
+        const int64_t g = row * P.n2 + i2;
+        const uint32_t t = (uint32_t)(((i0 / E) * P.t1 + i1 / E) * P.t2 + i2 / E);
+        bool seed = false;
+        if (P.tflags[t] & TF_SEED) {
+            const int p = (int)(((i0 % E) * E + i1 % E) * E + i2 % E);
+            seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
+        }
+        const double v = P.T[g];
+        const double a = fabs(v);
+        const uint8_t neg = v < 0.0 ? 0x80 : 0;
+        uint8_t st;
+        if (seed) {
+            st = 3 | neg;
+            mx = fmax(mx, a);
+        } else if (a < FMM_INF && a <= P.width) {
+            st = 2 | neg;
+            acc++;
+            mx = fmax(mx, a);
+        } else if (a < FMM_INF) {
+            st = 1 | neg;
+            P.T[g] = FMM_INF;
+        } else {
+            st = 0;
+        }
+        if (status) status[g] = st;
+    }
+    // block reduction
+    __shared__ unsigned long long s_acc[32];
+    __shared__ double s_mx[32];
+    acc = wave_sum(acc);
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_acc[wid] = acc;
+        s_mx[wid] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long a = 0;
+        double m = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
+            a += s_acc[w];
+            m = fmax(m, s_mx[w]);
+        }
+        if (a) atomicAdd(&P.ctrl->n_accepted, a);
+        atomicMax(&P.ctrl->max_abs_bits, dbits(m));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+
+static int num_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 1;
+    }
+    return cus;
+}
+
+hipError_t launch_prepare(const Params &P, const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, int E,
+                          bool validate, bool f64, hipStream_t s)
+{
+    const int cus = num_cus();
+    hipLaunchKernelGGL(k_init_ws, dim3(cus * 4), dim3(256), 0, s, P, E);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_inf, dim3(cus * 16), dim3(256), 0, s, P.T, P.n0 * P.n1 * P.n2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n_seeds > 0) {
+        const int64_t blocks = std::min<int64_t>((n_seeds + 255) / 256, (int64_t)cus * 16);
+        hipLaunchKernelGGL(k_seeds, dim3((unsigned)blocks), dim3(256), 0, s, P, seed_idx, seed_val, n_seeds, E);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (validate) {
+        if (f64)
+            hipLaunchKernelGGL(k_validate<double>, dim3(cus * 8), dim3(256), 0, s, P);
+        else
+            hipLaunchKernelGGL(k_validate<float>, dim3(cus * 8), dim3(256), 0, s, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_out)
+{
+    static int occ = -1;
+    auto kern = k_driver<E, NW, FT>;
+    if (occ < 0) {
+        int nb = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NW * 64, 0);
+        if (e != hipSuccess) return e;
+        occ = nb;
+    }
+    if (occ <= 0) return hipErrorInvalidConfiguration;
+    const unsigned grid = (unsigned)(occ * num_cus());
+    Params Pc = P;
+    void *args[] = {&Pc};
+    if (nwg_out) *nwg_out = grid;
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(NW * 64), args, 0, s);
+}
+
+hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
+{
+    switch (E) {
+    case 4: return f64 ? launch_driver_t<4, 16, double>(P, s, nwg_out) : launch_driver_t<4, 16, float>(P, s, nwg_out);
+    case 8: return f64 ? launch_driver_t<8, 8, double>(P, s, nwg_out) : launch_driver_t<8, 8, float>(P, s, nwg_out);
+    case 16: return f64 ? launch_driver_t<16, 1, double>(P, s, nwg_out) : launch_driver_t<16, 1, float>(P, s, nwg_out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_finalize(const Params &P, int E, uint8_t *status, hipStream_t s)
+{
+    const int cus = num_cus();
+    hipLaunchKernelGGL(k_finalize, dim3(cus * 16), dim3(256), 0, s, P, status, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_godunov(const double *a, const double *r, double *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, (int64_t)num_cus() * 32);
+    hipLaunchKernelGGL(k_eval_godunov, dim3((unsigned)blocks), dim3(256), 0, s, a, r, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace fmm

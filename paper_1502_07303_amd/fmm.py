@@ -1,0 +1,190 @@
+"""Python binding of ``libfmm.so`` (argument marshalling only).
+
+Every step of the solve runs in the HIP library; torch provides device memory
+and the current stream.  The library must have been built (``build.py``);
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_EDEVICE = 0, -1, -2, -3, -4, -5
+FMM_F32, FMM_F64 = 0, 1
+FMM_VALIDATE = 1
+
+DERR = {1: "seed index out of range", 2: "duplicate seed", 4: "non-finite seed value",
+        8: "non-finite speed", 16: "restart limit", 32: "barrier timeout", 64: "round cap",
+        128: "launch", 256: "time limit"}
+
+ST_FAR, ST_BAND, ST_ACCEPTED, ST_SEED, ST_NEG = 0, 1, 2, 3, 0x80
+
+
+class FmmOpts(ctypes.Structure):
+    _fields_ = [("band_width", ctypes.c_double), ("stride", ctypes.c_double),
+                ("tile_edge", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("time_limit_s", ctypes.c_uint32)]
+
+
+class FmmStats(ctypes.Structure):
+    _fields_ = [("n_accepted", ctypes.c_int64), ("n_restarts", ctypes.c_int64),
+                ("n_reopened", ctypes.c_int64), ("n_tile_marches", ctypes.c_int64),
+                ("n_solves", ctypes.c_int64), ("n_rounds", ctypes.c_int64),
+                ("max_abs_T", ctypes.c_double), ("device_error", ctypes.c_uint32),
+                ("tile_edge", ctypes.c_uint32), ("n_workgroups", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfmm.so and declare its C signatures; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_1502_07303_amd/build.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    lib.fmm_default_opts.argtypes = [ctypes.POINTER(FmmOpts)]
+    lib.fmm_default_opts.restype = None
+    lib.fmm_workspace_bytes.argtypes = [i64, i64, i64, i64, ctypes.POINTER(FmmOpts)]
+    lib.fmm_workspace_bytes.restype = ctypes.c_size_t
+    lib.fmm_solve.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, i64, ctypes.POINTER(FmmOpts),
+                              P, P, P, ctypes.c_size_t, P]
+    lib.fmm_solve.restype = ctypes.c_int
+    lib.fmm_get_stats.argtypes = [P, ctypes.POINTER(FmmStats), P]
+    lib.fmm_get_stats.restype = ctypes.c_int
+    lib.fmm_eval_godunov.argtypes = [P, P, P, i64, P]
+    lib.fmm_eval_godunov.restype = ctypes.c_int
+    lib.fmm_strerror.argtypes = [ctypes.c_int]
+    lib.fmm_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().fmm_strerror(int(code)).decode()
+
+
+def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, validate=False,
+              time_limit_s=0) -> FmmOpts:
+    o = FmmOpts()
+    load_library().fmm_default_opts(ctypes.byref(o))
+    o.band_width = float(band_width)
+    o.stride = 0.0 if stride is None else float(stride)
+    o.tile_edge = int(tile_edge)
+    o.max_restarts = int(max_restarts)
+    o.flags = FMM_VALIDATE if validate else 0
+    o.time_limit_s = int(time_limit_s)
+    return o
+
+
+def workspace_bytes(shape, n_seeds, opts: Optional[FmmOpts] = None) -> int:
+    n0, n1, n2 = shape
+    return int(load_library().fmm_workspace_bytes(n0, n1, n2, n_seeds, ctypes.byref(opts) if opts else None))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """Reusable solve context: owns the workspace for one grid shape and the
+    option set, so repeated solves allocate nothing."""
+
+    def __init__(self, shape, n_seeds, h, band_width=math.inf, stride=None, tile_edge=0, max_restarts=0,
+                 validate=False, device="cuda", time_limit_s=0):
+        self.lib = load_library()
+        self.shape = tuple(int(x) for x in shape)
+        self.h = float(h)
+        self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s)
+        nbytes = workspace_bytes(self.shape, n_seeds, self.opts)
+        if nbytes == 0:
+            raise FmmError(FMM_EINVAL, "invalid problem or options")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+        self.nbytes = nbytes
+
+    def solve_into(self, F: torch.Tensor, seed_idx: torch.Tensor, seed_val: torch.Tensor, T: torch.Tensor,
+                   status: Optional[torch.Tensor] = None, stream=None) -> None:
+        """Enqueue a solve on the current (or given) stream; no synchronisation."""
+        if F.dtype == torch.float32:
+            dt = FMM_F32
+        elif F.dtype == torch.float64:
+            dt = FMM_F64
+        else:
+            raise FmmError(FMM_EINVAL, f"unsupported speed dtype {F.dtype}")
+        if tuple(F.shape) != self.shape or not F.is_contiguous() or not F.is_cuda:
+            raise FmmError(FMM_EINVAL, "F must be a contiguous CUDA tensor of the solver's shape")
+        if seed_idx.dtype != torch.int64 or seed_val.dtype != torch.float64:
+            raise FmmError(FMM_EINVAL, "seed_idx must be int64 and seed_val float64")
+        if not (seed_idx.is_contiguous() and seed_val.is_contiguous()) or seed_idx.numel() != seed_val.numel():
+            raise FmmError(FMM_EINVAL, "seed arrays must be contiguous and of equal length")
+        if T.dtype != torch.float64 or tuple(T.shape) != self.shape or not T.is_contiguous():
+            raise FmmError(FMM_EINVAL, "T must be a contiguous float64 tensor of the solver's shape")
+        if status is not None and (status.dtype != torch.uint8 or tuple(status.shape) != self.shape
+                                   or not status.is_contiguous()):
+            raise FmmError(FMM_EINVAL, "status must be a contiguous uint8 tensor of the solver's shape")
+        ns = seed_idx.numel()
+        n0, n1, n2 = self.shape
+        rc = self.lib.fmm_solve(n0, n1, n2, self.h, _ptr(F), dt, _ptr(seed_idx) if ns else None,
+                                _ptr(seed_val) if ns else None, ns, ctypes.byref(self.opts), _ptr(T),
+                                _ptr(status), _ptr(self.ws), self.nbytes, _stream_handle(stream))
+        if rc != FMM_OK:
+            raise FmmError(rc, f"fmm_solve: {strerror(rc)}")
+
+    def stats(self, stream=None, check=True) -> FmmStats:
+        """Synchronise the stream and read the statistics of the last solve."""
+        st = FmmStats()
+        rc = self.lib.fmm_get_stats(_ptr(self.ws), ctypes.byref(st), _stream_handle(stream))
+        if check and rc != FMM_OK:
+            bits = [m for b, m in DERR.items() if st.device_error & b]
+            raise FmmError(rc, f"fmm_solve failed on the device: {strerror(rc)} ({', '.join(bits)})")
+        return st
+
+
+def solve(F: torch.Tensor, h: float, seed_idx: torch.Tensor, seed_val: torch.Tensor, band_width=math.inf,
+          stride=None, tile_edge=0, max_restarts=0, validate=False, with_status=True, check=True,
+          time_limit_s=0):
+    """One solve on F's device; returns (T, status, stats) after synchronising."""
+    s = Solver(F.shape, seed_idx.numel(), h, band_width, stride, tile_edge, max_restarts, validate, F.device,
+               time_limit_s)
+    T = torch.empty(F.shape, dtype=torch.float64, device=F.device)
+    status = torch.empty(F.shape, dtype=torch.uint8, device=F.device) if with_status else None
+    s.solve_into(F, seed_idx, seed_val, T, status)
+    st = s.stats(check=check)
+    return T, status, st
+
+
+def eval_godunov(a: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
+    """Device local solver on (n, 3) upwind values and (n,) r = h/F."""
+    a = a.contiguous()
+    r = r.contiguous()
+    out = torch.empty(r.shape, dtype=torch.float64, device=r.device)
+    rc = load_library().fmm_eval_godunov(_ptr(a), _ptr(r), _ptr(out), r.numel(), _stream_handle())
+    if rc != FMM_OK:
+        raise FmmError(rc, f"fmm_eval_godunov: {strerror(rc)}")
+    return out

@@ -1,0 +1,122 @@
+"""The C ABI without a GPU: the library loads, exports what include/fmm.h
+declares, agrees with the header on struct layouts, and rejects bad
+arguments on the host before touching the device."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "fmm.h")
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    from paper_1502_07303_amd import fmm as m
+    m.load_library()
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmm_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(fmm):
+    names = declared_functions()
+    assert {"fmm_solve", "fmm_workspace_bytes", "fmm_get_stats", "fmm_strerror", "fmm_default_opts",
+            "fmm_eval_godunov"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", fmm.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (fmm_\w+)", out))
+    for n in names:
+        assert n in exported, n
+        assert hasattr(fmm.load_library(), n)
+
+
+def test_struct_layout_matches_header(fmm, tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include "fmm.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(fmm_opts), sizeof(fmm_stats),'
+                   ' offsetof(fmm_stats, max_abs_T), offsetof(fmm_stats, n_workgroups));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals == [ctypes.sizeof(fmm.FmmOpts), ctypes.sizeof(fmm.FmmStats),
+                    fmm.FmmStats.max_abs_T.offset, fmm.FmmStats.n_workgroups.offset]
+
+
+def test_default_opts(fmm):
+    o = fmm.FmmOpts()
+    fmm.load_library().fmm_default_opts(ctypes.byref(o))
+    assert math.isinf(o.band_width) and o.stride == 0.0 and o.tile_edge == 8
+    assert o.max_restarts == 0 and o.flags == 0
+
+
+def test_workspace_bytes(fmm):
+    lib = fmm.load_library()
+    w8 = lib.fmm_workspace_bytes(64, 64, 64, 1, None)
+    assert w8 > 0 and w8 % 256 == 0
+    o = fmm.make_opts(tile_edge=4)
+    w4 = lib.fmm_workspace_bytes(64, 64, 64, 1, ctypes.byref(o))
+    assert w4 > w8  # more tiles
+    # ragged grids round up to whole tiles
+    assert lib.fmm_workspace_bytes(65, 64, 64, 1, None) > w8
+    # invalid
+    assert lib.fmm_workspace_bytes(0, 64, 64, 1, None) == 0
+    assert lib.fmm_workspace_bytes(64, 64, 64, -1, None) == 0
+    bad = fmm.make_opts(tile_edge=5)
+    assert lib.fmm_workspace_bytes(64, 64, 64, 1, ctypes.byref(bad)) == 0
+    # 1024^3 with 8^3 tiles stays modest next to the grid arrays
+    big = lib.fmm_workspace_bytes(1024, 1024, 1024, 4, None)
+    assert 0 < big < 400 * 2 ** 20
+
+
+def _call(fmm, **kw):
+    lib = fmm.load_library()
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: host validation fails first
+    args = dict(n0=8, n1=8, n2=8, h=0.1, F=fake, dt=fmm.FMM_F64, idx=fake, val=fake, ns=1, opts=None,
+                T=fake, st=None, ws=fake, wsb=1 << 30, stream=None)
+    args.update(kw)
+    o = args["opts"]
+    return lib.fmm_solve(args["n0"], args["n1"], args["n2"], args["h"], args["F"], args["dt"], args["idx"],
+                         args["val"], args["ns"], ctypes.byref(o) if o is not None else None, args["T"],
+                         args["st"], args["ws"], args["wsb"], args["stream"])
+
+
+@pytest.mark.parametrize("kw", [
+    {"n0": 0}, {"n2": -3}, {"h": 0.0}, {"h": -1.0}, {"h": math.nan}, {"h": math.inf},
+    {"F": None}, {"T": None}, {"ws": None}, {"dt": 7}, {"ns": -1}, {"idx": None}, {"val": None},
+    {"ws": ctypes.c_void_p(0x100010)},  # misaligned workspace
+])
+def test_host_rejects_bad_arguments(fmm, kw):
+    assert _call(fmm, **kw) == fmm.FMM_EINVAL
+
+
+@pytest.mark.parametrize("opt", [dict(band_width=-1.0), dict(band_width=math.nan), dict(stride=math.nan),
+                                 dict(tile_edge=6), dict(max_restarts=-2)])
+def test_host_rejects_bad_options(fmm, opt):
+    o = fmm.make_opts()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    assert _call(fmm, opts=o) == fmm.FMM_EINVAL
+
+
+def test_host_reports_small_workspace(fmm):
+    assert _call(fmm, wsb=64) == fmm.FMM_ENOMEM
+
+
+def test_strerror(fmm):
+    assert fmm.strerror(fmm.FMM_OK) == "ok"
+    assert "workspace" in fmm.strerror(fmm.FMM_ENOMEM)
+    assert fmm.strerror(12345) == "unknown status"
+
+
+def test_eval_godunov_rejects_null(fmm):
+    assert fmm.load_library().fmm_eval_godunov(None, None, None, 5, None) == fmm.FMM_EINVAL
+    assert fmm.load_library().fmm_eval_godunov(None, None, None, 0, None) == fmm.FMM_OK

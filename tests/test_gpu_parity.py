@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar (from the method's own accuracy claim, Sec. 5.2): identical status bytes
+(accepted set, band, seeds, sides) and max |T_gpu - T_oracle| <= 1e-12 max|T|
+over the accepted points.  Floating point never decides the accepted set in
+these cases except at the band edge, which the two-sided cases check
+explicitly."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import accepted_mask, backward_error, load_golden, parity_report, seed_mask
+from paper_1502_07303_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_07303_amd import fmm as m
+    m.load_library()
+    return m
+
+
+def gpu_solve(fmm, w, **kw):
+    dev = torch.device("cuda:0")
+    kw.setdefault("time_limit_s", 30)
+    T, st, stats = fmm.solve(w.F.to(dev), w.h, w.seed_idx.to(dev), w.seed_val.to(dev),
+                             band_width=w.width, **kw)
+    return T.cpu().numpy(), st.cpu().numpy(), stats
+
+
+def oracle_solve(oracle_mod, w):
+    F, idx, val = w.numpy()
+    T, st, stats, _ = oracle_mod.solve(F, w.h, idx, val, width=w.width)
+    return T, st, stats
+
+
+def assert_parity(Tg, sg, To, so, tol=TOL, allow_edge=None):
+    rep = parity_report(Tg, sg, To, so)
+    if not rep["same_status"]:
+        diff = np.flatnonzero(sg.reshape(-1) != so.reshape(-1))
+        if allow_edge is not None:
+            # points whose |T| lies within rounding of the band width may flip
+            edge = np.abs(np.abs(To.reshape(-1)[diff]) - allow_edge) <= 1e-12 * allow_edge
+            assert np.all(edge | np.isinf(To.reshape(-1)[diff])), rep
+        else:
+            raise AssertionError(f"status differs at {len(diff)} points, first {diff[:5]}: "
+                                 f"gpu {sg.reshape(-1)[diff[:5]]} oracle {so.reshape(-1)[diff[:5]]}")
+    assert rep["rel"] <= tol, rep
+    return rep
+
+
+# --------------------------------------------------------------------------
+
+def test_device_local_solver_bitwise(fmm, oracle_mod):
+    """Device G against the oracle's G on random arguments: identical bits
+    (correctly rounded sqrt and division, no contraction on either side)."""
+    rng = np.random.default_rng(0)
+    n = 1 << 20
+    r = rng.uniform(1e-4, 1.0, size=n)
+    base = rng.uniform(0, 50, size=(n, 1))
+    a = base + rng.uniform(0, 1.5, size=(n, 3)) * r[:, None]
+    a[rng.random(n) < 0.2, 2] = np.inf
+    a[rng.random(n) < 0.1, 1] = np.inf
+    tie = rng.random(n) < 0.1
+    a[tie, 1] = a[tie, 0]
+    expect = oracle_mod.godunov_batch(a, r)
+    got = fmm.eval_godunov(torch.from_numpy(a).cuda(), torch.from_numpy(r).cuda()).cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), expect.view(np.uint64))
+
+
+def test_single_tile_infinite_stride_two_restarts(fmm, oracle_mod):
+    """Sec. 5.3: one subdomain with an infinite stride finishes in 2 restarts."""
+    (row,) = load_golden("restarts_single_subdomain.txt")
+    assert math.isinf(row[0]) and row[1] == 1
+    w = inputs.random_small((8, 8, 8), n_sources=2, seed=3)
+    Tg, sg, st = gpu_solve(fmm, w, stride=math.inf, tile_edge=8)
+    To, so, _ = oracle_solve(oracle_mod, w)
+    assert st.n_restarts == int(row[2])
+    assert_parity(Tg, sg, To, so)
+
+
+@pytest.mark.parametrize("stride_h", [2.0, math.inf, 0.5])
+def test_point_source_64(fmm, oracle_mod, stride_h):
+    w = inputs.point_source(64)
+    Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h)
+    To, so, sto = oracle_solve(oracle_mod, w)
+    assert st.n_accepted == sto.n_accepted == 64 ** 3 - 1
+    assert_parity(Tg, sg, To, so)
+
+
+@pytest.mark.parametrize("edge", [4, 8, 16])
+@pytest.mark.parametrize("shape,seed,nsrc,dtype,zero", [
+    ((16, 16, 16), 0, 1, torch.float64, 0.0),
+    ((37, 29, 45), 1, 3, torch.float32, 0.0),
+    ((33, 40, 18), 2, 2, torch.float64, 0.08),
+])
+def test_random_speed_parity(fmm, oracle_mod, edge, shape, seed, nsrc, dtype, zero):
+    w = inputs.random_small(shape, n_sources=nsrc, seed=seed, dtype=dtype, zero_frac=zero)
+    To, so, _ = oracle_solve(oracle_mod, w)
+    for stride_h in (0.5, 2.0, math.inf):
+        Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, tile_edge=edge)
+        assert_parity(Tg, sg, To, so)
+
+
+@pytest.mark.parametrize("width", [0.1, math.inf])
+def test_two_sided_spheres(fmm, oracle_mod, width):
+    w = inputs.spheres(n=48, n_spheres=5, seed=1, width=width)
+    To, so, _ = oracle_solve(oracle_mod, w)
+    Tg, sg, st = gpu_solve(fmm, w)
+    assert np.any(so & 0x80)
+    assert_parity(Tg, sg, To, so, allow_edge=width if math.isfinite(width) else None)
+
+
+def test_sphere_reinit_256(fmm, oracle_mod):
+    """The 256^3 signed-distance reinitialisation workload (8 spheres, band 0.1)."""
+    w = inputs.spheres(n=256)
+    To, so, sto = oracle_solve(oracle_mod, w)
+    Tg, sg, st = gpu_solve(fmm, w)
+    rep = assert_parity(Tg, sg, To, so, allow_edge=w.width)
+    print("spheres_256", rep, st.as_dict(), flush=True)
+
+
+def test_deterministic(fmm):
+    w = inputs.random_small((40, 33, 47), n_sources=3, seed=9)
+    T1, s1, _ = gpu_solve(fmm, w, stride=2 * w.h)
+    T2, s2, _ = gpu_solve(fmm, w, stride=2 * w.h)
+    assert np.array_equal(T1.view(np.uint64), T2.view(np.uint64)) and np.array_equal(s1, s2)
+
+
+def test_no_seeds(fmm):
+    dev = torch.device("cuda:0")
+    F = torch.ones((9, 10, 11), dtype=torch.float64, device=dev)
+    e = torch.empty(0, dtype=torch.int64, device=dev)
+    T, st, stats = fmm.solve(F, 0.1, e, e.to(torch.float64), time_limit_s=30)
+    assert torch.all(torch.isinf(T)) and torch.all(st == 0) and stats.n_accepted == 0
+
+
+def test_residual_and_seeds_verbatim(fmm):
+    w = inputs.random_small((30, 31, 29), n_sources=4, seed=12)
+    w.seed_val[:] = torch.tensor([0.0, -0.0, 0.01, 0.02], dtype=torch.float64)
+    Tg, sg, st = gpu_solve(fmm, w)
+    F, idx, val = w.numpy()
+    acc = accepted_mask(sg)
+    err = backward_error(Tg, F, w.h, acc)
+    assert np.max(np.abs(err[acc])) <= 1e-13 * np.max(np.abs(Tg[acc]))
+    got = Tg.reshape(-1)[idx]
+    assert np.array_equal(got.view(np.uint64), val.view(np.uint64))
+    assert np.all(sg.reshape(-1)[idx] == 3)
+
+
+@pytest.mark.parametrize("bad", ["dup", "range", "nan_seed", "nan_speed"])
+def test_device_input_errors(fmm, bad):
+    dev = torch.device("cuda:0")
+    F = torch.ones((12, 12, 12), dtype=torch.float64, device=dev)
+    idx = torch.tensor([5, 700], dtype=torch.int64, device=dev)
+    val = torch.zeros(2, dtype=torch.float64, device=dev)
+    if bad == "dup":
+        idx[1] = 5
+    elif bad == "range":
+        idx[1] = 12 ** 3
+    elif bad == "nan_seed":
+        val[1] = math.nan
+    else:
+        F[3, 4, 5] = math.nan
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.solve(F, 0.1, idx, val, validate=True, time_limit_s=30)
+    assert ei.value.code == fmm.FMM_EDEVICE
+
+
+def test_restart_limit(fmm):
+    w = inputs.point_source(32)
+    dev = torch.device("cuda:0")
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.solve(w.F.to(dev), w.h, w.seed_idx.to(dev), w.seed_val.to(dev), max_restarts=1, time_limit_s=30)
+    assert ei.value.code == fmm.FMM_ENOCONV
