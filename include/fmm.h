@@ -47,6 +47,7 @@ typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
 
 /* Option flags. */
 #define FMM_VALIDATE 1u /* check on the device that every F value is finite */
+#define FMM_TIMING 2u   /* record HIP events around each stage; fmm_get_stats reports them */
 
 /* Device error bits (fmm_stats.device_error). */
 #define FMM_DERR_SEED_RANGE 1u  /* a seed index outside [0, n0*n1*n2)       */
@@ -68,6 +69,12 @@ typedef struct {
      * band in each restart; a value <= 0 selects 2h, the paper's
      * recommended stride (Sec. 5.5). */
     double stride;
+    /* Step of the ordered relaxation inside a tile march, in world units: a
+     * cell becomes a source of its tile once its value is within `inner` of
+     * the tile's smallest pending band value (an implementation parameter,
+     * not one of the paper's).  INFINITY relaxes the whole band of the
+     * restart at once; a value <= 0 selects h/2. */
+    double inner_stride;
     /* Edge of the cubic grid tiles that play the subdomains: 4, 8 or 16;
      * 0 selects 8. */
     int32_t tile_edge;
@@ -91,6 +98,10 @@ typedef struct {
     uint32_t device_error;  /* FMM_DERR_* bits                                     */
     uint32_t tile_edge;     /* tile edge actually used                             */
     int64_t n_workgroups;   /* persistent workgroups of the restart driver        */
+    /* With FMM_TIMING: milliseconds of the preparation kernels (workspace
+     * reset, T = +inf, seeds), of the restart driver and of the finalize
+     * kernel, from HIP events on the solve's stream; -1 otherwise. */
+    double ms_prepare, ms_driver, ms_finalize;
 } fmm_stats;
 
 /* Fill *opts with the defaults: band_width = INFINITY, stride = 2h (<= 0),
@@ -125,7 +136,9 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
 
 /* Synchronise `stream`, copy the statistics of the last solve that used
  * `workspace` into *out (host), and return FMM_OK, or FMM_ENOCONV /
- * FMM_EDEVICE when the device recorded an error. */
+ * FMM_EDEVICE when the device recorded an error.  The stage timings of
+ * FMM_TIMING belong to the last timed solve on this workspace; the events
+ * are host-side objects the library keeps per workspace address. */
 int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream);
 
 /* The local solver on the device (Alg. 11, Eqs. 2-7): out[i] = G(a[3i],

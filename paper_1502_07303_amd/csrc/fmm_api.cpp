@@ -3,6 +3,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "../../include/fmm.h"
 #include "fmm_internal.h"
 
@@ -20,15 +23,16 @@ bool opts_ok(const fmm_opts *o)
 {
     if (!o) return true;
     if (isnan(o->band_width) || o->band_width < 0.0) return false;
-    if (isnan(o->stride)) return false;
+    if (isnan(o->stride) || isnan(o->inner_stride)) return false;
     if (!(o->tile_edge == 0 || o->tile_edge == 4 || o->tile_edge == 8 || o->tile_edge == 16)) return false;
     if (o->max_restarts < 0) return false;
-    if (o->flags & ~(uint32_t)FMM_VALIDATE) return false;
+    if (o->flags & ~(uint32_t)(FMM_VALIDATE | FMM_TIMING)) return false;
     return true;
 }
 
 Params make_params(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, double *T, const Layout &L,
-                   void *ws, double width, double stride, int64_t max_restarts, uint32_t time_limit_s)
+                   void *ws, double width, double stride, double inner, int64_t max_restarts,
+                   uint32_t time_limit_s)
 {
     char *b = (char *)ws;
     Params P;
@@ -44,6 +48,7 @@ Params make_params(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, 
     P.h = h;
     P.width = width;
     P.stride = stride;
+    P.inner = inner;
     P.max_restarts = max_restarts;
     // the driver reads the 100 MHz constant clock
     P.time_limit_ticks = 100000000ull * (unsigned long long)(time_limit_s ? time_limit_s : 300u);
@@ -62,6 +67,26 @@ Params make_params(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, 
     return P;
 }
 
+// HIP events of timed solves, keyed by workspace address (host objects only).
+struct StageEvents {
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool valid = false;
+};
+std::mutex g_ev_mu;
+std::unordered_map<const void *, StageEvents> g_events;
+
+StageEvents *events_for(const void *ws, bool create)
+{
+    std::lock_guard<std::mutex> lk(g_ev_mu);
+    auto it = g_events.find(ws);
+    if (it != g_events.end()) return &it->second;
+    if (!create) return nullptr;
+    StageEvents e;
+    for (auto &x : e.ev)
+        if (hipEventCreate(&x) != hipSuccess) return nullptr;
+    return &(g_events[ws] = e);
+}
+
 }  // namespace
 
 extern "C" {
@@ -72,6 +97,7 @@ void fmm_default_opts(fmm_opts *o)
     memset(o, 0, sizeof *o);
     o->band_width = INFINITY;
     o->stride = 0.0;
+    o->inner_stride = 0.0;
     o->tile_edge = 8;
     o->max_restarts = 0;
     o->flags = 0;
@@ -108,14 +134,31 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
     if (workspace_bytes < L.total) return FMM_ENOMEM;
     const double stride = (o.stride > 0.0) ? o.stride : 2.0 * h;
     const int64_t maxr = o.max_restarts > 0 ? (int64_t)o.max_restarts : 0;
-    Params P = make_params(n0, n1, n2, h, F, T_out, L, workspace, o.band_width, stride, maxr, o.time_limit_s);
+    const double inner = (o.inner_stride > 0.0) ? o.inner_stride : 0.5 * h;
+    Params P = make_params(n0, n1, n2, h, F, T_out, L, workspace, o.band_width, stride, inner, maxr, o.time_limit_s);
     hipStream_t s = (hipStream_t)stream;
     const bool f64 = F_dtype == FMM_F64;
+    StageEvents *ev = nullptr;
+    if (o.flags & FMM_TIMING) {
+        ev = events_for(workspace, true);
+        if (!ev) return FMM_EHIP;
+        ev->valid = false;
+    } else if ((ev = events_for(workspace, false)) != nullptr) {
+        ev->valid = false;
+        ev = nullptr;
+    }
+    if (ev && hipEventRecord(ev->ev[0], s) != hipSuccess) return FMM_EHIP;
     if (launch_prepare(P, seed_idx, seed_val, n_seeds, E, (o.flags & FMM_VALIDATE) != 0, f64, s) != hipSuccess)
         return FMM_EHIP;
+    if (ev && hipEventRecord(ev->ev[1], s) != hipSuccess) return FMM_EHIP;
     uint32_t nwg = 0;
     if (launch_driver(P, E, f64, s, &nwg) != hipSuccess) return FMM_EHIP;
+    if (ev && hipEventRecord(ev->ev[2], s) != hipSuccess) return FMM_EHIP;
     if (launch_finalize(P, E, status_out, s) != hipSuccess) return FMM_EHIP;
+    if (ev) {
+        if (hipEventRecord(ev->ev[3], s) != hipSuccess) return FMM_EHIP;
+        ev->valid = true;
+    }
     return FMM_OK;
 }
 
@@ -139,6 +182,17 @@ int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream)
     out->device_error = c.error | c.error_run;
     out->tile_edge = c.tile_edge;
     out->n_workgroups = (int64_t)c.nwg;
+    out->ms_prepare = out->ms_driver = out->ms_finalize = -1.0;
+    if (StageEvents *ev = events_for(workspace, false)) {
+        float t[3];
+        if (ev->valid && hipEventElapsedTime(&t[0], ev->ev[0], ev->ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&t[1], ev->ev[1], ev->ev[2]) == hipSuccess &&
+            hipEventElapsedTime(&t[2], ev->ev[2], ev->ev[3]) == hipSuccess) {
+            out->ms_prepare = t[0];
+            out->ms_driver = t[1];
+            out->ms_finalize = t[2];
+        }
+    }
     if (out->device_error & ERR_NOCONV) return FMM_ENOCONV;
     if (out->device_error) return FMM_EDEVICE;
     return FMM_OK;

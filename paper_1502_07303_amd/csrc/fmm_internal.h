@@ -33,6 +33,8 @@ struct Ctrl {
     unsigned long long n_reopen;
     unsigned long long n_accepted;
     unsigned long long max_abs_bits;
+    // cycle counters of builds with FMM_PROFILE defined (zero otherwise)
+    alignas(128) unsigned long long prof[16];
 };
 
 // Per-tile record: smallest |T| per side among the tile's pending band values
@@ -111,7 +113,7 @@ struct Params {
     int32_t t0, t1, t2;
     uint32_t ntiles;
     uint32_t mask_words;
-    double h, width, stride;
+    double h, width, stride, inner;
     int64_t max_restarts;
     unsigned long long time_limit_ticks;  // restart-driver wall-clock limit (100 MHz ticks)
     double *T;

@@ -150,7 +150,7 @@ template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int 
 }
 
 constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
-constexpr int KR = 8;      // candidates per lane held in registers per relaxation step
+constexpr int KR = 2;      // candidates per lane held in registers per relaxation step
 constexpr int MAX_ROUNDS = 1 << 16;
 
 enum : uint8_t { FL_SEED = 1, FL_UPD = 2, FL_CHG = 4 };
@@ -173,7 +173,18 @@ template <int NW> struct WgShared {
     uint32_t ok;
 };
 
+#ifdef FMM_PROFILE
+#define PROF_CLOCK(x) const unsigned long long x = clock64()
+#define PROF_ADD(i, v) (ws.prof[i] += (v))
+#else
+#define PROF_CLOCK(x)
+#define PROF_ADD(i, v)
+#endif
+
 struct WaveState {
+#ifdef FMM_PROFILE
+    unsigned long long prof[16];
+#endif
     uint32_t nL, nD;      // staged entries (wave-uniform)
     uint32_t pending;     // tiles newly dirtied for the next restart
     double gmin0, gmin1;  // running min of band minima
@@ -268,16 +279,18 @@ template <int E, typename FT> __device__ __forceinline__ int compact(WaveLds<E, 
     return (int)total;
 }
 
-// Mark the updatable interior neighbours of interior point p (domain cell d).
-template <int E, typename FT> __device__ __forceinline__ void mark_nbrs(WaveLds<E, FT> &L, int p, int d)
+// Mark the updatable interior neighbours of interior point p (domain cell d)
+// that lie downwind of the value magnitude a: only they can use p as an
+// upwind point (the |T_lmn| > |T_ijk| guard of Alg. 10).
+template <int E, typename FT> __device__ __forceinline__ void mark_nbrs(WaveLds<E, FT> &L, int p, int d, double a)
 {
     using G = Geo<E>;
-    if (L.fl[d - G::OX] & FL_UPD) L.cf[p - E * E] = 1;
-    if (L.fl[d + G::OX] & FL_UPD) L.cf[p + E * E] = 1;
-    if (L.fl[d - G::OY] & FL_UPD) L.cf[p - E] = 1;
-    if (L.fl[d + G::OY] & FL_UPD) L.cf[p + E] = 1;
-    if (L.fl[d - G::OZ] & FL_UPD) L.cf[p - 1] = 1;
-    if (L.fl[d + G::OZ] & FL_UPD) L.cf[p + 1] = 1;
+    if ((L.fl[d - G::OX] & FL_UPD) && fabs(L.T[d - G::OX]) > a) L.cf[p - E * E] = 1;
+    if ((L.fl[d + G::OX] & FL_UPD) && fabs(L.T[d + G::OX]) > a) L.cf[p + E * E] = 1;
+    if ((L.fl[d - G::OY] & FL_UPD) && fabs(L.T[d - G::OY]) > a) L.cf[p - E] = 1;
+    if ((L.fl[d + G::OY] & FL_UPD) && fabs(L.T[d + G::OY]) > a) L.cf[p + E] = 1;
+    if ((L.fl[d - G::OZ] & FL_UPD) && fabs(L.T[d - G::OZ]) > a) L.cf[p - 1] = 1;
+    if ((L.fl[d + G::OZ] & FL_UPD) && fabs(L.T[d + G::OZ]) > a) L.cf[p + 1] = 1;
 }
 
 // A domain cell is a source of the relaxation when it is a seed, or when its
@@ -324,24 +337,152 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, doubl
     double best = ap;
     bool neg = vp < 0.0;
     bool improved = false;
-    if (fmin(am[0], fmin(am[1], am[2])) < FMM_INF) {
-        double u = godunov(am[0], am[1], am[2], r);
-        if (u < best || (u == best && !neg && best < FMM_INF)) {
+    // one local solve per side that has an upwind point (kept as a loop so
+    // the solver is emitted once)
+#pragma unroll 1
+    for (int side = 0; side < 2; side++) {
+        const double x = side == 0 ? am[0] : ap3[0];
+        const double y = side == 0 ? am[1] : ap3[1];
+        const double z = side == 0 ? am[2] : ap3[2];
+        if (!(fmin(x, fmin(y, z)) < FMM_INF)) continue;
+        const double u = godunov(x, y, z, r);
+        const bool take = u < best || (side == 0 && u == best && !neg && best < FMM_INF);
+        if (take) {
             best = u;
-            neg = true;
-            improved = true;
-        }
-    }
-    if (fmin(ap3[0], fmin(ap3[1], ap3[2])) < FMM_INF) {
-        double u = godunov(ap3[0], ap3[1], ap3[2], r);
-        if (u < best) {
-            best = u;
-            neg = false;
+            neg = side == 0;
             improved = true;
         }
     }
     out = neg ? -best : best;
     return improved;
+}
+
+// Jacobi relaxation at level th until no candidate improves; returns the
+// number of rounds.  Every evaluation of a round reads the values of the
+// previous round, so the result does not depend on lane order.
+template <int E, typename FT>
+__device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, const double th[2], const double lastb[2],
+                                     WaveState &ws)
+{
+    using G = Geo<E>;
+    const int lane = threadIdx.x & 63;
+    int cur = 0;
+    int n = compact(L, L.list[0]);
+    int rounds = 0;
+    while (n > 0) {
+        if (++rounds > MAX_ROUNDS) {
+            if (lane == 0) atomicOr(&P.ctrl->error_run, ERR_ROUNDS);
+            break;
+        }
+        for (int base = 0; base < n; base += 64 * KR) {
+            double nv[KR];
+            bool ch[KR];
+#pragma unroll
+            for (int j = 0; j < KR; j++) {
+                const int k = base + lane + 64 * j;
+                ch[j] = false;
+                nv[j] = 0.0;
+                if (k < n) {
+                    ch[j] = eval_point(L, (int)L.list[cur][k], P.h, th, nv[j]);
+                    ws.n_solve++;
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int j = 0; j < KR; j++) {
+                const int k = base + lane + 64 * j;
+                if (k < n && ch[j]) {
+                    const int p = L.list[cur][k];
+                    const int d = G::domp(p);
+                    const double old = L.T[d];
+                    if (is_source(old, 0, th) || fabs(old) <= (old < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
+                    L.T[d] = nv[j];
+                    L.fl[d] |= FL_CHG;
+                    if (is_source(nv[j], 0, th)) mark_nbrs(L, p, d, fabs(nv[j]));
+                }
+            }
+            wave_sync();
+        }
+        cur ^= 1;
+        n = compact(L, L.list[cur]);
+    }
+    return rounds;
+}
+
+// Smallest pending band value per side above level th: interior band values,
+// and halo values next to an interior cell that is not yet a source (they
+// become sources of this tile later).  Wave-uniform result.
+template <int E, typename FT>
+__device__ __forceinline__ void band_min(const WaveLds<E, FT> &L, const double th[2], double &m0, double &m1)
+{
+    using G = Geo<E>;
+    constexpr int V = G::V, FACE = G::FACE;
+    const int lane = threadIdx.x & 63;
+    double a0 = FMM_INF, a1 = FMM_INF;
+    for (int p = lane; p < V; p += 64) {
+        const int d = G::domp(p);
+        if (!(L.fl[d] & FL_UPD)) continue;
+        const double v = L.T[d];
+        const double a = fabs(v);
+        if (a < FMM_INF) {
+            if (v < 0.0) {
+                if (a > th[0]) a0 = fmin(a0, a);
+            } else if (a > th[1]) {
+                a1 = fmin(a1, a);
+            }
+        }
+    }
+    for (int q = lane; q < 6 * FACE; q += 64) {
+        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+        int c0, c1, c2;
+        face_cell<E>(f, u, w, c0, c1, c2);
+        const int d = G::dom(c0, c1, c2);
+        const double v = L.T[d];
+        const double a = fabs(v);
+        if (!(a < FMM_INF) || (L.fl[d] & FL_SEED)) continue;
+        if (a <= (v < 0.0 ? th[0] : th[1])) continue;
+        face_inner<E>(f, c0, c1, c2);
+        const int di = G::dom(c0, c1, c2);
+        if (!(L.fl[di] & FL_UPD) || is_source(L.T[di], 0, th)) continue;
+        if (v < 0.0)
+            a0 = fmin(a0, a);
+        else
+            a1 = fmin(a1, a);
+    }
+    m0 = wave_min(a0);
+    m1 = wave_min(a1);
+}
+
+// Mark the candidates next to cells whose value lies in (lo, hi] of their
+// side: they become sources when the level rises from lo to hi.
+template <int E, typename FT>
+__device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double lo[2], const double hi[2])
+{
+    using G = Geo<E>;
+    constexpr int V = G::V, FACE = G::FACE;
+    const int lane = threadIdx.x & 63;
+    for (int p = lane; p < V; p += 64) {
+        const int d = G::domp(p);
+        if (!(L.fl[d] & FL_UPD)) continue;
+        const double v = L.T[d];
+        const double a = fabs(v);
+        const int s = v < 0.0 ? 0 : 1;
+        if (a < FMM_INF && a > lo[s] && a <= hi[s]) mark_nbrs(L, p, d, a);
+    }
+    for (int q = lane; q < 6 * FACE; q += 64) {
+        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+        int c0, c1, c2;
+        face_cell<E>(f, u, w, c0, c1, c2);
+        const int d = G::dom(c0, c1, c2);
+        const double v = L.T[d];
+        const double a = fabs(v);
+        const int s = v < 0.0 ? 0 : 1;
+        if (!(a < FMM_INF && a > lo[s] && a <= hi[s]) || (L.fl[d] & FL_SEED)) continue;
+        face_inner<E>(f, c0, c1, c2);
+        const int di = G::dom(c0, c1, c2);
+        if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > a) L.cf[(c0 * E + c1) * E + c2] = 1;
+    }
+    wave_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -351,7 +492,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, doubl
 // the tile's pending band minimum (the heap top of Alg. 16).
 
 template <int E, typename FT>
-__device__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int mode, uint32_t dbits,
+__device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int mode, uint32_t dbits,
                            const double bnd[2], const double lastb[2], uint32_t epoch, WaveState &ws,
                            uint32_t *listNext, uint32_t *cntNext, uint32_t *dlist, uint32_t *cntD,
                            uint32_t *dprod)
@@ -373,6 +514,7 @@ __device__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int m
     const bool hasSeed = (P.tflags[t] & TF_SEED) != 0;
     const unsigned long long *mask = P.mask + (size_t)t * P.mask_words;
 
+    PROF_CLOCK(t_begin);
     // ---- load interior
     for (int p = lane; p < V; p += 64) {
         const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
@@ -425,84 +567,70 @@ __device__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int m
     }
     wave_sync();
 
-    // ---- initial candidates: neighbours of cells that became sources since
-    // this tile's last march (seeds count as new only in the first phase), and
-    // interior cells next to a halo face that changed.
+    // ---- ordered relaxation.  Sources at level th are the seeds and the
+    // cells with |T| <= th of their side (the KNOWN-class points of Alg. 11).
+    // The level starts at the bound of the tile's previous march and climbs to
+    // this restart's bound in steps th = (smallest pending band value) + inner,
+    // so values become sources in increasing order, as the heap of Alg. 12
+    // would release them, up to the step width.
+    PROF_CLOCK(t_loaded);
+    PROF_ADD(2, t_loaded - t_begin);
     const bool init = mode == MODE_INIT;
-    for (int p = lane; p < V; p += 64) {
-        const int d = G::domp(p);
-        const double v = L.T[d];
-        const uint8_t fl = L.fl[d];
-        if (is_source(v, fl, bnd)) {
-            const double a = fabs(v);
-            const bool before = (fl & FL_SEED) ? !init : a <= (v < 0.0 ? lastb[0] : lastb[1]);
-            if (!before) mark_nbrs(L, p, d);
+    double th[2] = {init ? -1.0 : lastb[0], init ? -1.0 : lastb[1]};
+    if (init) {
+        // Alg. 9: the neighbours of every seed (in the tile or its halo).
+        for (int p = lane; p < V; p += 64) {
+            const int d = G::domp(p);
+            if (L.fl[d] & FL_SEED) mark_nbrs(L, p, d, fabs(L.T[d]));
         }
-    }
-    for (int q = lane; q < 6 * FACE; q += 64) {
-        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-        int c0, c1, c2;
-        face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = G::dom(c0, c1, c2);
-        face_inner<E>(f, c0, c1, c2);
-        const int pi = (c0 * E + c1) * E + c2;
-        const int di = G::dom(c0, c1, c2);
-        if (!(L.fl[di] & FL_UPD)) continue;
-        const double v = L.T[d];
-        const uint8_t fl = L.fl[d];
-        bool mark = (dbits >> f) & 1u;
-        if (!mark && is_source(v, fl, bnd)) {
-            const double a = fabs(v);
-            const bool before = (fl & FL_SEED) ? !init : a <= (v < 0.0 ? lastb[0] : lastb[1]);
-            mark = !before;
+        for (int q = lane; q < 6 * FACE; q += 64) {
+            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            int c0, c1, c2;
+            face_cell<E>(f, u, w, c0, c1, c2);
+            const int d = G::dom(c0, c1, c2);
+            face_inner<E>(f, c0, c1, c2);
+            const int di = G::dom(c0, c1, c2);
+            if ((L.fl[d] & FL_SEED) && (L.fl[di] & FL_UPD) && fabs(L.T[di]) > fabs(L.T[d]))
+                L.cf[(c0 * E + c1) * E + c2] = 1;
         }
-        if (mark) L.cf[pi] = 1;
+    } else if (dbits) {
+        // interior cells next to a halo face whose values changed (Alg. 15)
+        for (int q = lane; q < 6 * FACE; q += 64) {
+            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            if (!((dbits >> f) & 1u)) continue;
+            int c0, c1, c2;
+            face_cell<E>(f, u, w, c0, c1, c2);
+            const double vh = fabs(L.T[G::dom(c0, c1, c2)]);
+            face_inner<E>(f, c0, c1, c2);
+            const int di = G::dom(c0, c1, c2);
+            if ((L.fl[di] & FL_UPD) && vh < FMM_INF && fabs(L.T[di]) > vh) L.cf[(c0 * E + c1) * E + c2] = 1;
+        }
     }
     wave_sync();
-
-    // ---- relaxation rounds (Jacobi: all evaluations of a round read the
-    // values of the previous round, so the result is independent of lane order)
-    int cur = 0;
-    int n = compact(L, L.list[0]);
     int rounds = 0;
-    while (n > 0) {
-        if (++rounds > MAX_ROUNDS) {
-            if (lane == 0) atomicOr(&P.ctrl->error_run, ERR_ROUNDS);
-            break;
-        }
-        for (int base = 0; base < n; base += 64 * KR) {
-            double nv[KR];
-            bool ch[KR];
-#pragma unroll
-            for (int j = 0; j < KR; j++) {
-                const int k = base + lane + 64 * j;
-                ch[j] = false;
-                nv[j] = 0.0;
-                if (k < n) {
-                    ch[j] = eval_point(L, (int)L.list[cur][k], P.h, bnd, nv[j]);
-                    ws.n_solve++;
-                }
-            }
-            wave_sync();
-#pragma unroll
-            for (int j = 0; j < KR; j++) {
-                const int k = base + lane + 64 * j;
-                if (k < n && ch[j]) {
-                    const int p = L.list[cur][k];
-                    const int d = G::domp(p);
-                    const double old = L.T[d];
-                    if (is_source(old, 0, bnd) || fabs(old) <= (old < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
-                    L.T[d] = nv[j];
-                    L.fl[d] |= FL_CHG;
-                    if (is_source(nv[j], 0, bnd)) mark_nbrs(L, p, d);
-                }
-            }
-            wave_sync();
-        }
-        cur ^= 1;
-        n = compact(L, L.list[cur]);
+    double tm0, tm1;
+    PROF_CLOCK(t_marked);
+    PROF_ADD(3, t_marked - t_loaded);
+    for (;;) {
+        PROF_CLOCK(t_r0);
+        rounds += relax(P, L, th, lastb, ws);
+        PROF_CLOCK(t_r1);
+        PROF_ADD(4, t_r1 - t_r0);
+        PROF_ADD(8, 1);
+        band_min(L, th, tm0, tm1);
+        const bool more0 = tm0 < FMM_INF && tm0 <= bnd[0];
+        const bool more1 = tm1 < FMM_INF && tm1 <= bnd[1];
+        if (!(more0 || more1)) break;
+        const double nt[2] = {more0 ? fmin(tm0 + P.inner, bnd[0]) : th[0],
+                              more1 ? fmin(tm1 + P.inner, bnd[1]) : th[1]};
+        mark_new_sources(L, th, nt);
+        th[0] = nt[0];
+        th[1] = nt[1];
+        PROF_CLOCK(t_r2);
+        PROF_ADD(5, t_r2 - t_r1);
     }
-    ws.n_round += rounds;
+    PROF_CLOCK(t_levels);
+    ws.n_round += (unsigned long long)rounds;
     ws.n_march++;
 
     // ---- write back changed interior points; collect changed faces
@@ -522,42 +650,6 @@ __device__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int m
     for (int f = 0; f < 6; f++)
         if (__ballot((fmask >> f) & 1u)) faces |= 1u << f;
 
-    // ---- pending band minimum per side: interior band values above the
-    // bound, and halo values above the bound next to an interior point that
-    // is not yet a source (they become sources of this tile in a later restart)
-    double tm0 = FMM_INF, tm1 = FMM_INF;
-    for (int p = lane; p < V; p += 64) {
-        const int d = G::domp(p);
-        if (!(L.fl[d] & FL_UPD)) continue;
-        const double v = L.T[d];
-        const double a = fabs(v);
-        if (a < FMM_INF) {
-            if (v < 0.0) {
-                if (a > bnd[0]) tm0 = fmin(tm0, a);
-            } else if (a > bnd[1]) {
-                tm1 = fmin(tm1, a);
-            }
-        }
-    }
-    for (int q = lane; q < 6 * FACE; q += 64) {
-        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-        int c0, c1, c2;
-        face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = G::dom(c0, c1, c2);
-        const double v = L.T[d];
-        const double a = fabs(v);
-        if (!(a < FMM_INF) || (L.fl[d] & FL_SEED)) continue;
-        if (a <= (v < 0.0 ? bnd[0] : bnd[1])) continue;
-        face_inner<E>(f, c0, c1, c2);
-        const int di = G::dom(c0, c1, c2);
-        if (!(L.fl[di] & FL_UPD) || is_source(L.T[di], 0, bnd)) continue;
-        if (v < 0.0)
-            tm0 = fmin(tm0, a);
-        else
-            tm1 = fmin(tm1, a);
-    }
-    tm0 = wave_min(tm0);
-    tm1 = wave_min(tm1);
     if (lane == 0) {
         TileMeta m;
         m.tmin[0] = tm0;
@@ -601,13 +693,15 @@ __device__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int m
         if (oe != epoch) stage_push(L.stL, ws.nL, t, cntNext, listNext);
     }
     wave_sync();
+    PROF_CLOCK(t_end);
+    PROF_ADD(6, t_end - t_levels);
 }
 
 // ---------------------------------------------------------------------------
 // Persistent restart driver (Alg. 16).
 
 template <int E, int NW, typename FT>
-__device__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
+__device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
                           const uint32_t *items, uint32_t nitems, const double bnd[2], WaveState &ws)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -619,6 +713,7 @@ __device__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, i
     uint32_t *dcons = mode == MODE_M1 ? P.dirty0 : P.dirty1;
     uint32_t *dprod = mode == MODE_M1 ? P.dirty1 : P.dirty0;
     const uint32_t gw = blockIdx.x * NW + wid, GW = gridDim.x * NW;
+    PROF_CLOCK(t_phase0);
 
     for (uint32_t i = gw; i < nitems; i += GW) {
         if (ld_acq(&c->abort)) break;
@@ -643,6 +738,7 @@ __device__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, i
                     oe = bcast0(oe);
                     if (oe != epoch) stage_push(L.stL, ws.nL, t, &nxt.live_len, listNext);
                 }
+                PROF_ADD(7, 1);
                 continue;
             }
         }
@@ -650,6 +746,8 @@ __device__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, i
                           &cur.d_len, dprod);
     }
 
+    PROF_CLOCK(t_phase1);
+    PROF_ADD(0, t_phase1 - t_phase0);
     // ---- workgroup epilogue: one atomic per list / reduction per workgroup
     if (lane == 0) {
         S.cntL[wid] = ws.nL;
@@ -703,60 +801,92 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
     ws.pending = 0;
     ws.gmin0 = ws.gmin1 = FMM_INF;
     ws.n_march = ws.n_round = ws.n_solve = ws.n_reopen = 0;
+#ifdef FMM_PROFILE
+    for (int k = 0; k < 16; k++) ws.prof[k] = 0;
+#endif
 
     const unsigned long long t_start = wall_clock64();
     if (blockIdx.x == 0 && threadIdx.x == 0) c->nwg = nwg;
-    if (ld_acq(&c->error) == 0) {
-        // Heap initialisation (Alg. 9): only seeds are sources.
-        const double nob[2] = {-1.0, -1.0};
-        run_phase<E, NW, FT>(P, L, s_g, MODE_INIT, 0u, P.list0, ld_acq(&c->slot[0].live_len), nob, ws);
-        if (grid_barrier(c, gen, nwg, &s_g.ok)) {
-            for (uint32_t r = 1;; r++) {
-                Slot &S = c->slot[r % 3];
-                const double g0 = bitsd(ld_acq64(&S.gmin[0])), g1 = bitsd(ld_acq64(&S.gmin[1]));
-                const uint32_t pend = ld_acq(&S.pending);
-                const uint32_t len = ld_acq(&S.live_len);
-                if (blockIdx.x == 0 && threadIdx.x == 0) {
-                    Slot &Z = c->slot[(r + 2) % 3];
-                    Z.gmin[0] = Z.gmin[1] = dbits(FMM_INF);
-                    Z.live_len = Z.pending = Z.d_len = 0;
+    // Phase sequence: heap initialisation (Alg. 9: only seeds are sources),
+    // then per restart r = 1, 2, ...: march-1 over the live tiles, march-2
+    // over the tiles whose halo changed (Alg. 16).  One call site keeps the
+    // march inlined once.
+    int mode = MODE_INIT;
+    uint32_t r = 0;
+    double bnd[2] = {-1.0, -1.0};
+    const uint32_t *items = P.list0;
+    uint32_t nitems = ld_acq(&c->slot[0].live_len);
+    bool run = ld_acq(&c->error) == 0;
+    while (run) {
+        PROF_CLOCK(t_p0);
+        run_phase<E, NW, FT>(P, L, s_g, mode, r, items, nitems, bnd, ws);
+        PROF_CLOCK(t_p1);
+        const bool passed = grid_barrier(c, gen, nwg, &s_g.ok);
+        PROF_CLOCK(t_p2);
+        PROF_ADD(1, t_p2 - t_p0);
+        PROF_ADD(9, t_p2 - t_p1);
+        if (!passed) break;
+        if (mode == MODE_M1) {
+            mode = MODE_M2;
+            items = P.dlist;
+            nitems = ld_acq(&c->slot[r % 3].d_len);
+            continue;
+        }
+        r++;
+        Slot &S = c->slot[r % 3];
+        const double g0 = bitsd(ld_acq64(&S.gmin[0])), g1 = bitsd(ld_acq64(&S.gmin[1]));
+        const uint32_t pend = ld_acq(&S.pending);
+        const uint32_t len = ld_acq(&S.live_len);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            Slot &Z = c->slot[(r + 2) % 3];
+            Z.gmin[0] = Z.gmin[1] = dbits(FMM_INF);
+            Z.live_len = Z.pending = Z.d_len = 0;
+        }
+        // Alg. 16 exit test: both sides have no band value within the width
+        // (an empty band reports +inf) and no tile is left dirty.
+        const bool done0 = !(g0 < FMM_INF && g0 <= P.width);
+        const bool done1 = !(g1 < FMM_INF && g1 <= P.width);
+        if (done0 && done1 && pend == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) c->restarts = r;
+            break;
+        }
+        if (P.max_restarts > 0 && (int64_t)r > P.max_restarts) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                atomicOr(&c->error_run, ERR_NOCONV);
+                c->restarts = r;
+            }
+            break;
+        }
+        // Safety net: workgroup 0 aborts a solve that exceeds the time limit
+        // (one clock read, shared through LDS); the others leave at their
+        // next barrier.
+        if (blockIdx.x == 0) {
+            if (threadIdx.x == 0) s_g.ok = (wall_clock64() - t_start > P.time_limit_ticks) ? 1u : 0u;
+            __syncthreads();
+            const bool late = s_g.ok != 0;
+            __syncthreads();
+            if (late) {
+                if (threadIdx.x == 0) {
+                    atomicOr(&c->error_run, ERR_TIMEOUT);
+                    atomicExch(&c->abort, 1u);
+                    c->restarts = r;
                 }
-                // Alg. 16 exit test: both sides have no band value within the
-                // width (an empty band reports +inf) and no tile is left dirty.
-                const bool done0 = !(g0 < FMM_INF && g0 <= P.width);
-                const bool done1 = !(g1 < FMM_INF && g1 <= P.width);
-                if (done0 && done1 && pend == 0) {
-                    if (blockIdx.x == 0 && threadIdx.x == 0) c->restarts = r;
-                    break;
-                }
-                if (P.max_restarts > 0 && (int64_t)r > P.max_restarts) {
-                    if (blockIdx.x == 0 && threadIdx.x == 0) {
-                        atomicOr(&c->error_run, ERR_NOCONV);
-                        c->restarts = r;
-                    }
-                    break;
-                }
-                // Safety net: workgroup 0 aborts a solve that exceeds the time
-                // limit; the others leave at their next barrier.
-                if (blockIdx.x == 0 && wall_clock64() - t_start > P.time_limit_ticks) {
-                    if (threadIdx.x == 0) {
-                        atomicOr(&c->error_run, ERR_TIMEOUT);
-                        atomicExch(&c->abort, 1u);
-                        c->restarts = r;
-                    }
-                    break;
-                }
-                // bound = min(minval + stride, width) per side (Alg. 16)
-                const double bnd[2] = {fmin(g0 + P.stride, P.width), fmin(g1 + P.stride, P.width)};
-                run_phase<E, NW, FT>(P, L, s_g, MODE_M1, r, (r & 1) ? P.list1 : P.list0, len, bnd, ws);
-                if (!grid_barrier(c, gen, nwg, &s_g.ok)) break;
-                run_phase<E, NW, FT>(P, L, s_g, MODE_M2, r, P.dlist, ld_acq(&S.d_len), bnd, ws);
-                if (!grid_barrier(c, gen, nwg, &s_g.ok)) break;
+                break;
             }
         }
+        // bound = min(minval + stride, width) per side (Alg. 16)
+        bnd[0] = fmin(g0 + P.stride, P.width);
+        bnd[1] = fmin(g1 + P.stride, P.width);
+        mode = MODE_M1;
+        items = (r & 1) ? P.list1 : P.list0;
+        nitems = len;
     }
     // ---- statistics
     const unsigned long long ns = wave_sum(ws.n_solve), nr = wave_sum(ws.n_reopen);
+#ifdef FMM_PROFILE
+    if (lane == 0)
+        for (int k = 0; k < 16; k++) atomicAdd(&c->prof[k], ws.prof[k]);
+#endif
     if (lane == 0) {
         atomicAdd(&c->n_march, ws.n_march);
         atomicAdd(&c->n_round, ws.n_round);
@@ -787,6 +917,7 @@ __global__ void k_init_ws(Params P, int E)
             c->slot[k].live_len = c->slot[k].pending = c->slot[k].d_len = 0;
         }
         c->n_march = c->n_solve = c->n_round = c->n_reopen = 0;
+        for (int k = 0; k < 16; k++) c->prof[k] = 0;
         c->n_accepted = 0;
         c->max_abs_bits = 0;
     }
@@ -989,7 +1120,7 @@ template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Pa
 hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
 {
     switch (E) {
-    case 4: return f64 ? launch_driver_t<4, 16, double>(P, s, nwg_out) : launch_driver_t<4, 16, float>(P, s, nwg_out);
+    case 4: return f64 ? launch_driver_t<4, 8, double>(P, s, nwg_out) : launch_driver_t<4, 8, float>(P, s, nwg_out);
     case 8: return f64 ? launch_driver_t<8, 8, double>(P, s, nwg_out) : launch_driver_t<8, 8, float>(P, s, nwg_out);
     case 16: return f64 ? launch_driver_t<16, 1, double>(P, s, nwg_out) : launch_driver_t<16, 1, float>(P, s, nwg_out);
     default: return hipErrorInvalidValue;

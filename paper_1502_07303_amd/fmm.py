@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfmm.so")
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_EDEVICE = 0, -1, -2, -3, -4, -5
 FMM_F32, FMM_F64 = 0, 1
 FMM_VALIDATE = 1
+FMM_TIMING = 2
 
 DERR = {1: "seed index out of range", 2: "duplicate seed", 4: "non-finite seed value",
         8: "non-finite speed", 16: "restart limit", 32: "barrier timeout", 64: "round cap",
@@ -29,7 +30,7 @@ ST_FAR, ST_BAND, ST_ACCEPTED, ST_SEED, ST_NEG = 0, 1, 2, 3, 0x80
 
 class FmmOpts(ctypes.Structure):
     _fields_ = [("band_width", ctypes.c_double), ("stride", ctypes.c_double),
-                ("tile_edge", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
+                ("inner_stride", ctypes.c_double), ("tile_edge", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("time_limit_s", ctypes.c_uint32)]
 
 
@@ -38,7 +39,9 @@ class FmmStats(ctypes.Structure):
                 ("n_reopened", ctypes.c_int64), ("n_tile_marches", ctypes.c_int64),
                 ("n_solves", ctypes.c_int64), ("n_rounds", ctypes.c_int64),
                 ("max_abs_T", ctypes.c_double), ("device_error", ctypes.c_uint32),
-                ("tile_edge", ctypes.c_uint32), ("n_workgroups", ctypes.c_int64)]
+                ("tile_edge", ctypes.c_uint32), ("n_workgroups", ctypes.c_int64),
+                ("ms_prepare", ctypes.c_double), ("ms_driver", ctypes.c_double),
+                ("ms_finalize", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -84,14 +87,15 @@ def strerror(code: int) -> str:
 
 
 def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, validate=False,
-              time_limit_s=0) -> FmmOpts:
+              time_limit_s=0, timing=False, inner_stride=None) -> FmmOpts:
     o = FmmOpts()
     load_library().fmm_default_opts(ctypes.byref(o))
     o.band_width = float(band_width)
     o.stride = 0.0 if stride is None else float(stride)
+    o.inner_stride = 0.0 if inner_stride is None else float(inner_stride)
     o.tile_edge = int(tile_edge)
     o.max_restarts = int(max_restarts)
-    o.flags = FMM_VALIDATE if validate else 0
+    o.flags = (FMM_VALIDATE if validate else 0) | (FMM_TIMING if timing else 0)
     o.time_limit_s = int(time_limit_s)
     return o
 
@@ -115,11 +119,12 @@ class Solver:
     option set, so repeated solves allocate nothing."""
 
     def __init__(self, shape, n_seeds, h, band_width=math.inf, stride=None, tile_edge=0, max_restarts=0,
-                 validate=False, device="cuda", time_limit_s=0):
+                 validate=False, device="cuda", time_limit_s=0, timing=False, inner_stride=None):
         self.lib = load_library()
         self.shape = tuple(int(x) for x in shape)
         self.h = float(h)
-        self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s)
+        self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s, timing,
+                              inner_stride)
         nbytes = workspace_bytes(self.shape, n_seeds, self.opts)
         if nbytes == 0:
             raise FmmError(FMM_EINVAL, "invalid problem or options")
@@ -168,10 +173,10 @@ class Solver:
 
 def solve(F: torch.Tensor, h: float, seed_idx: torch.Tensor, seed_val: torch.Tensor, band_width=math.inf,
           stride=None, tile_edge=0, max_restarts=0, validate=False, with_status=True, check=True,
-          time_limit_s=0):
+          time_limit_s=0, inner_stride=None):
     """One solve on F's device; returns (T, status, stats) after synchronising."""
     s = Solver(F.shape, seed_idx.numel(), h, band_width, stride, tile_edge, max_restarts, validate, F.device,
-               time_limit_s)
+               time_limit_s, inner_stride=inner_stride)
     T = torch.empty(F.shape, dtype=torch.float64, device=F.device)
     status = torch.empty(F.shape, dtype=torch.uint8, device=F.device) if with_status else None
     s.solve_into(F, seed_idx, seed_val, T, status)
