@@ -57,7 +57,7 @@ def read_traffic(kernel_tag):
 def kernel_tag():
     import hashlib
     h = hashlib.sha256()
-    for f in ("fmm_kernels.hip", "fmm_internal.h"):
+    for f in ("fmm_kernels.hip", "fmm_internal.h", "fmm_api.cpp"):
         with open(os.path.join(ROOT, "paper_1502_07303_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-crop", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="GiB for a plain device copy, timed as achievable-HBM context and used to "
+                         "calibrate HBM byte counters")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -109,6 +112,24 @@ def main():
     from paper_1502_07303_amd import fmm, inputs
 
     dev = torch.device("cuda:0")
+    copy_probe = None
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe * 2 ** 30) // 8 * 8
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_copy = e0.elapsed_time(e1)
+        copy_probe = {"bytes_read": nbytes, "bytes_written": nbytes, "ms": round(ms_copy, 4),
+                      "GBs": round(2 * nbytes / (ms_copy / 1e3) / 1e9, 1)}
+        log(f"copy probe: {2 * nbytes / 2**30:.1f} GiB moved in {ms_copy:.3f} ms = {copy_probe['GBs']} GB/s")
+        del a, b
+        torch.cuda.empty_cache()
     log(f"generating random-speed workload n={args.n} on {torch.cuda.get_device_name(0)}")
     t0 = time.perf_counter()
     w = inputs.random_speed(n=args.n, seed=args.seed, device=dev)
@@ -186,6 +207,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_copy_probe": copy_probe,
         "solve": {"accepted": n_acc, "points": N, "restarts": int(stats.n_restarts),
                   "tile_marches": int(stats.n_tile_marches), "solves": int(stats.n_solves),
                   "rounds": int(stats.n_rounds), "reopened": int(stats.n_reopened),

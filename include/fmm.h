@@ -73,7 +73,7 @@ typedef struct {
      * cell becomes a source of its tile once its value is within `inner` of
      * the tile's smallest pending band value (an implementation parameter,
      * not one of the paper's).  INFINITY relaxes the whole band of the
-     * restart at once; a value <= 0 selects h/2. */
+     * restart at once; a value <= 0 selects INFINITY (fastest measured). */
     double inner_stride;
     /* Edge of the cubic grid tiles that play the subdomains: 4, 8 or 16;
      * 0 selects 8. */

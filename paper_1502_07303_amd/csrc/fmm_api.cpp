@@ -134,7 +134,7 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
     if (workspace_bytes < L.total) return FMM_ENOMEM;
     const double stride = (o.stride > 0.0) ? o.stride : 2.0 * h;
     const int64_t maxr = o.max_restarts > 0 ? (int64_t)o.max_restarts : 0;
-    const double inner = (o.inner_stride > 0.0) ? o.inner_stride : 0.5 * h;
+    const double inner = (o.inner_stride > 0.0) ? o.inner_stride : INFINITY;
     Params P = make_params(n0, n1, n2, h, F, T_out, L, workspace, o.band_width, stride, inner, maxr, o.time_limit_s);
     hipStream_t s = (hipStream_t)stream;
     const bool f64 = F_dtype == FMM_F64;
