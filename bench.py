@@ -138,7 +138,7 @@ def main():
     N = w.F.numel()
     stride = args.stride_h * w.h
     solver = fmm.Solver(w.shape, w.seed_idx.numel(), w.h, band_width=w.width, stride=stride,
-                        tile_edge=args.tile, timing=True, device=dev)
+                        tile_edge=args.tile, timing=True, device=dev, speed_dtype=w.F.dtype)
     T = torch.empty(w.shape, dtype=torch.float64, device=dev)
     status = torch.empty(w.shape, dtype=torch.uint8, device=dev)
 

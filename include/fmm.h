@@ -48,6 +48,10 @@ typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
 /* Option flags. */
 #define FMM_VALIDATE 1u /* check on the device that every F value is finite */
 #define FMM_TIMING 2u   /* record HIP events around each stage; fmm_get_stats reports them */
+/* Run one march per restart instead of Alg. 16's two: tiles whose halo
+ * received new values are marched in the next restart rather than in a
+ * second march after the exchange.  Same result; different cost balance. */
+#define FMM_ONE_MARCH 4u
 
 /* Device error bits (fmm_stats.device_error). */
 #define FMM_DERR_SEED_RANGE 1u  /* a seed index outside [0, n0*n1*n2)       */
@@ -109,8 +113,11 @@ typedef struct {
 void fmm_default_opts(fmm_opts *opts);
 
 /* Bytes of device workspace fmm_solve() needs for this problem (0 if the
- * arguments are invalid).  `opts` may be NULL for the defaults. */
-size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, const fmm_opts *opts);
+ * arguments are invalid).  `opts` may be NULL for the defaults.  The
+ * workspace holds tiled working copies of T and F, so it is about
+ * (8 + sizeof(F)) bytes per grid point plus the per-tile bookkeeping. */
+size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, fmm_dtype F_dtype,
+                           const fmm_opts *opts);
 
 /* Solve.  Inputs (device):
  *   F         n0*n1*n2 speeds of type F_dtype; F <= 0 (or NaN) marks an
@@ -121,7 +128,7 @@ size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, 
  *   seed_val  their values; the sign selects the side (value < 0 is the
  *             negative side; +0 and -0 are positive).  Both sides march in
  *             one pass (Sec. 3); the two sides must be separated by the seeds.
- * Outputs (device):
+ * Outputs (device), written once by the last kernel of the solve:
  *   T_out       n0*n1*n2 FP64; accepted points and seeds hold their signed
  *               values (seeds verbatim), all other points +INFINITY.
  *   status_out  n0*n1*n2 bytes or NULL: bits 0-1 FAR=0, BAND=1, ACCEPTED=2,

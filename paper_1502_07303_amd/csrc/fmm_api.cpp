@@ -1,5 +1,6 @@
 // C ABI of libfmm (declared in include/fmm.h): argument validation, workspace
-// carving and the enqueue sequence init -> seeds -> restart driver -> finalize.
+// carving and the enqueue sequence: workspace reset, tiled speeds, seeds ->
+// restart driver -> finalize.
 #include <math.h>
 #include <string.h>
 
@@ -26,7 +27,7 @@ bool opts_ok(const fmm_opts *o)
     if (isnan(o->stride) || isnan(o->inner_stride)) return false;
     if (!(o->tile_edge == 0 || o->tile_edge == 4 || o->tile_edge == 8 || o->tile_edge == 16)) return false;
     if (o->max_restarts < 0) return false;
-    if (o->flags & ~(uint32_t)(FMM_VALIDATE | FMM_TIMING)) return false;
+    if (o->flags & ~(uint32_t)(FMM_VALIDATE | FMM_TIMING | FMM_ONE_MARCH)) return false;
     return true;
 }
 
@@ -49,6 +50,7 @@ Params make_params(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, 
     P.width = width;
     P.stride = stride;
     P.inner = inner;
+    P.two_march = 1;
     P.max_restarts = max_restarts;
     // the driver reads the 100 MHz constant clock
     P.time_limit_ticks = 100000000ull * (unsigned long long)(time_limit_s ? time_limit_s : 300u);
@@ -60,6 +62,11 @@ Params make_params(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, 
     P.dirty1 = (uint32_t *)(b + L.off_dirty1);
     P.epoch = (uint32_t *)(b + L.off_epoch);
     P.tflags = (uint32_t *)(b + L.off_flags);
+    P.visit = (uint32_t *)(b + L.off_visit);
+    P.text = (unsigned long long *)(b + L.off_text);
+    P.Tt = (double *)(b + L.off_Tt);
+    P.Ft = (void *)(b + L.off_Ft);
+    P.Zf = (double *)(b + L.off_Zf);
     P.mask = (unsigned long long *)(b + L.off_mask);
     P.list0 = (uint32_t *)(b + L.off_list0);
     P.list1 = (uint32_t *)(b + L.off_list1);
@@ -103,11 +110,13 @@ void fmm_default_opts(fmm_opts *o)
     o->flags = 0;
 }
 
-size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, const fmm_opts *opts)
+size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, fmm_dtype F_dtype,
+                           const fmm_opts *opts)
 {
     if (n_seeds < 0 || !opts_ok(opts)) return 0;
+    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return 0;
     Layout L;
-    if (!make_layout(n0, n1, n2, resolve_edge(opts), &L)) return 0;
+    if (!make_layout(n0, n1, n2, resolve_edge(opts), F_dtype == FMM_F64 ? 8 : 4, &L)) return 0;
     return L.total;
 }
 
@@ -130,12 +139,13 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
         fmm_default_opts(&o);
     const int E = resolve_edge(&o);
     Layout L;
-    if (!make_layout(n0, n1, n2, E, &L)) return FMM_EINVAL;
+    if (!make_layout(n0, n1, n2, E, F_dtype == FMM_F64 ? 8 : 4, &L)) return FMM_EINVAL;
     if (workspace_bytes < L.total) return FMM_ENOMEM;
     const double stride = (o.stride > 0.0) ? o.stride : 2.0 * h;
     const int64_t maxr = o.max_restarts > 0 ? (int64_t)o.max_restarts : 0;
     const double inner = (o.inner_stride > 0.0) ? o.inner_stride : INFINITY;
     Params P = make_params(n0, n1, n2, h, F, T_out, L, workspace, o.band_width, stride, inner, maxr, o.time_limit_s);
+    P.two_march = (o.flags & FMM_ONE_MARCH) ? 0 : 1;
     hipStream_t s = (hipStream_t)stream;
     const bool f64 = F_dtype == FMM_F64;
     StageEvents *ev = nullptr;

@@ -58,19 +58,22 @@ enum : uint32_t {
     ERR_TIMEOUT = 256u,
 };
 
-// Carving of the caller's workspace.
+// Carving of the caller's workspace.  Besides the per-tile bookkeeping it
+// holds the tiled working copies of T and F (each tile's E^3 values
+// contiguous, axis 2 fastest inside the tile) and, per tile, the two faces
+// normal to axis 2 (the only halo faces that are strided in the tiled layout).
 struct Layout {
     int E;
     int32_t t0, t1, t2;
     uint32_t ntiles;
     uint32_t mask_words;  // 64-bit seed-mask words per tile
-    size_t off_ctrl, off_meta, off_dirty0, off_dirty1, off_epoch, off_flags, off_mask, off_list0,
-        off_list1, off_dlist, total;
+    size_t off_ctrl, off_meta, off_dirty0, off_dirty1, off_epoch, off_flags, off_visit, off_text, off_mask,
+        off_list0, off_list1, off_dlist, off_Tt, off_Ft, off_Zf, total;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-inline bool make_layout(int64_t n0, int64_t n1, int64_t n2, int E, Layout *L)
+inline bool make_layout(int64_t n0, int64_t n1, int64_t n2, int E, size_t fsize, Layout *L)
 {
     if (n0 <= 0 || n1 <= 0 || n2 <= 0) return false;
     if (!(E == 4 || E == 8 || E == 16)) return false;
@@ -96,6 +99,10 @@ inline bool make_layout(int64_t n0, int64_t n1, int64_t n2, int E, Layout *L)
     o = align_up(o + 4 * nt, 256);
     L->off_flags = o;
     o = align_up(o + 4 * nt, 256);
+    L->off_visit = o;
+    o = align_up(o + 4 * nt, 256);
+    L->off_text = o;
+    o = align_up(o + 48 * nt, 256);
     L->off_mask = o;
     o = align_up(o + 8 * (size_t)L->mask_words * nt, 256);
     L->off_list0 = o;
@@ -104,6 +111,13 @@ inline bool make_layout(int64_t n0, int64_t n1, int64_t n2, int E, Layout *L)
     o = align_up(o + 4 * nt, 256);
     L->off_dlist = o;
     o = align_up(o + 4 * nt, 256);
+    const size_t V = (size_t)E * E * E;
+    L->off_Tt = o;
+    o = align_up(o + 8 * V * nt, 256);
+    L->off_Ft = o;
+    o = align_up(o + fsize * V * nt, 256);
+    L->off_Zf = o;
+    o = align_up(o + 8 * 2 * (size_t)E * E * nt, 256);
     L->total = o;
     return true;
 }
@@ -115,12 +129,20 @@ struct Params {
     uint32_t mask_words;
     double h, width, stride, inner;
     int64_t max_restarts;
+    int32_t two_march;  // second march of Alg. 16 after the exchange (1) or not (0)
     unsigned long long time_limit_ticks;  // restart-driver wall-clock limit (100 MHz ticks)
-    double *T;
-    const void *F;
+    double *T;        // output, row-major (written by the finalize kernel)
+    const void *F;    // input speeds, row-major
+    double *Tt;       // tiled working T
+    void *Ft;         // tiled speeds (type of F)
+    double *Zf;       // per tile: its i2 = 0 and i2 = E-1 faces
     Ctrl *ctrl;
     TileMeta *meta;
     uint32_t *dirty0, *dirty1, *epoch, *tflags;
+    uint32_t *visit;  // 0: never written; else 1 + the phase that first wrote the tile
+    // per tile, phase slot (phase % 3) and side: smallest band value a
+    // neighbour passed on in that phase, [(t * 3 + slot) * 2 + side]
+    unsigned long long *text;
     unsigned long long *mask;
     uint32_t *list0, *list1, *dlist;
 };

@@ -80,7 +80,7 @@ __global__ void k_eval_godunov(const double *__restrict__ a, const double *__res
 // ---------------------------------------------------------------------------
 // Small helpers.
 
-__device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+__device__ __forceinline__ unsigned long long bits_of(double x) { return (unsigned long long)__double_as_longlong(x); }
 __device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
 
 __device__ __forceinline__ void wave_sync()
@@ -149,6 +149,15 @@ template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int 
     else c2 = ic;
 }
 
+// Wavefronts per workgroup of the 8^3-tile driver (one workgroup per CU; LDS
+// bounds it at 10 for FP32 speeds and 9 for FP64).
+#ifndef FMM_E8_WAVES_F32
+#define FMM_E8_WAVES_F32 10
+#endif
+#ifndef FMM_E8_WAVES_F64
+#define FMM_E8_WAVES_F64 9
+#endif
+
 constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
 constexpr int KR = 2;      // candidates per lane held in registers per relaxation step
 constexpr int MAX_ROUNDS = 1 << 16;
@@ -164,6 +173,7 @@ template <int E, typename FT> struct WaveLds {
     uint8_t fl[Geo<E>::DV];               // FL_* per domain cell
     uint32_t stL[STAGE];                  // staged live-list appends
     uint32_t stD[STAGE];                  // staged dirty-list appends
+    unsigned long long bm[12];            // per face and side: smallest changed band value
 };
 
 template <int NW> struct WgShared {
@@ -253,30 +263,61 @@ template <int E, typename FT> __device__ __forceinline__ int compact(WaveLds<E, 
     constexpr int K = Geo<E>::K;
     const int lane = threadIdx.x & 63;
     uint32_t cnt = 0;
-    if (lane * K < Geo<E>::V) {
+    if constexpr (K % 8 == 0) {
+        // flags are 0/1 bytes: a 64-bit word holds 8 of them
+        unsigned long long *w = (unsigned long long *)&L.cf[lane * K];
+        unsigned long long x[K / 8];
 #pragma unroll
-        for (int j = 0; j < K; j++) cnt += L.cf[lane * K + j] != 0;
-    }
-    uint32_t pre = 0, total = 0;
-    const unsigned long long lt = (1ull << lane) - 1ull;
+        for (int j = 0; j < K / 8; j++) {
+            x[j] = w[j];
+            cnt += (uint32_t)__popcll(x[j]);
+        }
+        uint32_t pre = 0, total = 0;
+        const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
-    for (int b = 0; (1 << b) <= K; b++) {
-        unsigned long long m = __ballot((cnt >> b) & 1u);
-        pre += (uint32_t)__popcll(m & lt) << b;
-        total += (uint32_t)__popcll(m) << b;
-    }
-    if (cnt) {
+        for (int b = 0; (1 << b) <= K; b++) {
+            const unsigned long long m = __ballot((cnt >> b) & 1u);
+            pre += (uint32_t)__popcll(m & lt) << b;
+            total += (uint32_t)__popcll(m) << b;
+        }
 #pragma unroll
-        for (int j = 0; j < K; j++) {
-            int p = lane * K + j;
-            if (L.cf[p]) {
-                out[pre++] = (uint16_t)p;
-                L.cf[p] = 0;
+        for (int j = 0; j < K / 8; j++) {
+            unsigned long long y = x[j];
+            while (y) {
+                const int bit = __ffsll((long long)y) - 1;
+                out[pre++] = (uint16_t)(lane * K + j * 8 + (bit >> 3));
+                y &= y - 1;
+            }
+            if (x[j]) w[j] = 0ull;
+        }
+        wave_sync();
+        return (int)total;
+    } else {
+        if (lane * K < Geo<E>::V) {
+#pragma unroll
+            for (int j = 0; j < K; j++) cnt += L.cf[lane * K + j] != 0;
+        }
+        uint32_t pre = 0, total = 0;
+        const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int b = 0; (1 << b) <= K; b++) {
+            const unsigned long long m = __ballot((cnt >> b) & 1u);
+            pre += (uint32_t)__popcll(m & lt) << b;
+            total += (uint32_t)__popcll(m) << b;
+        }
+        if (cnt) {
+#pragma unroll
+            for (int j = 0; j < K; j++) {
+                const int p = lane * K + j;
+                if (L.cf[p]) {
+                    out[pre++] = (uint16_t)p;
+                    L.cf[p] = 0;
+                }
             }
         }
+        wave_sync();
+        return (int)total;
     }
-    wave_sync();
-    return (int)total;
 }
 
 // Mark the updatable interior neighbours of interior point p (domain cell d)
@@ -488,83 +529,125 @@ __device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double
 // ---------------------------------------------------------------------------
 // One activation of a tile by one wavefront: load tile + halo into LDS, relax
 // its band up to the restart bound (Alg. 12 via Alg. 10/11), write back the
-// changed points, flag neighbours whose halo changed (Alg. 13/14), and record
-// the tile's pending band minimum (the heap top of Alg. 16).
+// changed points, pass changed boundary values on to the neighbours (Alg.
+// 13-15), and record the tile's pending band minimum (the heap top of Alg. 16).
+//
+// Data of a neighbour tile is used only if that tile was first written in an
+// earlier phase (visit stamp); otherwise its cells count as +inf, which is a
+// valid upper bound, and the writer's flag makes this tile read them again.
 
 template <int E, typename FT>
 __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int mode, uint32_t dbits,
-                           const double bnd[2], const double lastb[2], uint32_t epoch, WaveState &ws,
-                           uint32_t *listNext, uint32_t *cntNext, uint32_t *dlist, uint32_t *cntD,
-                           uint32_t *dprod)
+                                           const double bnd[2], const double lastb[2], uint32_t epoch, uint32_t phase,
+                                           bool second, WaveState &ws, uint32_t *listNext, uint32_t *cntNext,
+                                           uint32_t *dlist, uint32_t *cntD, uint32_t *dprod)
 {
     using G = Geo<E>;
     constexpr int V = G::V, FACE = G::FACE;
     const int lane = threadIdx.x & 63;
-    const FT *__restrict__ Fg = (const FT *)P.F;
-    double *__restrict__ Tg = P.T;
+    const FT *__restrict__ Ft = (const FT *)P.Ft;
+    double *__restrict__ Tt = P.Tt;
 
     const int32_t tz = (int32_t)(t % (uint32_t)P.t2);
     const int32_t ty = (int32_t)((t / (uint32_t)P.t2) % (uint32_t)P.t1);
     const int32_t tx = (int32_t)(t / ((uint32_t)P.t2 * (uint32_t)P.t1));
-    const int64_t o0 = (int64_t)tx * E, o1 = (int64_t)ty * E, o2 = (int64_t)tz * E;
-    const int e0 = (int)min((int64_t)E, P.n0 - o0), e1 = (int)min((int64_t)E, P.n1 - o1),
-              e2 = (int)min((int64_t)E, P.n2 - o2);
-    const int64_t n12 = P.n1 * P.n2;
     const uint32_t tsx = (uint32_t)P.t1 * (uint32_t)P.t2, tsy = (uint32_t)P.t2;
     const bool hasSeed = (P.tflags[t] & TF_SEED) != 0;
+    const bool fresh = P.visit[t] == 0;  // never written: every cell is +inf
     const unsigned long long *mask = P.mask + (size_t)t * P.mask_words;
+    const size_t tbase = (size_t)t * V;
 
     PROF_CLOCK(t_begin);
-    // ---- load interior
-    for (int p = lane; p < V; p += 64) {
-        const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
-        const int d = G::dom(i0, i1, i2);
-        double v = FMM_INF;
-        FT f = (FT)0;
-        uint8_t fl = 0;
-        if (i0 < e0 && i1 < e1 && i2 < e2) {
-            const int64_t g = (o0 + i0) * n12 + (o1 + i1) * P.n2 + (o2 + i2);
-            v = Tg[g];
-            f = Fg[g];
-            const bool seed = hasSeed && ((mask[p >> 6] >> (p & 63)) & 1ull);
-            fl = seed ? FL_SEED : ((double)f > 0.0 ? FL_UPD : 0);
-        }
-        L.T[d] = v;
-        L.F[p] = f;
-        L.fl[d] = fl;
-        L.cf[p] = 0;
-    }
-    // ---- load the six face halos (+inf outside the grid)
-    for (int q = lane; q < 6 * FACE; q += 64) {
-        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-        const int ax = f >> 1;
-        const bool plus = f & 1;
-        int c0, c1, c2;
-        face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = G::dom(c0, c1, c2);
-        double v = FMM_INF;
-        uint8_t fl = 0;
-        // in-face extent (ragged tiles) and the halo coordinate inside the grid
-        const int ua = ax == 0 ? e1 : e0, wa = ax == 2 ? e1 : e2;
-        const int64_t gh = ax == 0 ? o0 + c0 : ax == 1 ? o1 + c1 : o2 + c2;
-        const int64_t na = ax == 0 ? P.n0 : ax == 1 ? P.n1 : P.n2;
-        if (u < ua && w < wa && gh >= 0 && gh < na) {
-            const int64_t g = (o0 + c0) * n12 + (o1 + c1) * P.n2 + (o2 + c2);
-            v = Tg[g];
-            const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
-            const uint32_t tnb = plus ? t + ts : t - ts;
-            if (P.tflags[tnb] & TF_SEED) {
-                int n0c = c0, n1c = c1, n2c = c2;
-                if (ax == 0) n0c = plus ? 0 : E - 1;
-                else if (ax == 1) n1c = plus ? 0 : E - 1;
-                else n2c = plus ? 0 : E - 1;
-                const int pn = (n0c * E + n1c) * E + n2c;
-                if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
+    // ---- load the tile and its six face halos in one round trip: every
+    // address is inside the workspace, so all loads are issued first and the
+    // visit/seed selections are applied afterwards.  Axis-0 faces are
+    // contiguous E^2 runs of the neighbour tile, axis-1 faces E runs of E,
+    // axis-2 faces come from the neighbour's face buffer; +inf outside the
+    // grid or for a tile not yet written in an earlier phase.
+    constexpr int NI = (V + 63) / 64, NF = (6 * FACE + 63) / 64;
+    constexpr int CI = NI < 8 ? NI : 8, CF = NF < 8 ? NF : 8;
+    for (int j0 = 0; j0 < NI; j0 += CI) {
+        double vi[CI];
+        FT fi[CI];
+#pragma unroll
+        for (int j = 0; j < CI; j++) {
+            const int p = lane + 64 * (j0 + j);
+            if (p < V) {
+                vi[j] = Tt[tbase + p];
+                fi[j] = Ft[tbase + p];
             }
         }
-        L.T[d] = v;
-        L.fl[d] = fl;
+#pragma unroll
+        for (int j = 0; j < CI; j++) {
+            const int p = lane + 64 * (j0 + j);
+            if (p < V) {
+                const int d = G::domp(p);
+                const bool seed = hasSeed && ((mask[p >> 6] >> (p & 63)) & 1ull);
+                L.T[d] = fresh ? FMM_INF : vi[j];
+                L.F[p] = fi[j];
+                L.fl[d] = seed ? FL_SEED : ((double)fi[j] > 0.0 ? FL_UPD : 0);
+                L.cf[p] = 0;
+            }
+        }
     }
+    for (int j0 = 0; j0 < NF; j0 += CF) {
+        double vh[CF];
+        uint32_t vis_h[CF], tf_h[CF];
+#pragma unroll
+        for (int j = 0; j < CF; j++) {
+            const int q = lane + 64 * (j0 + j);
+            vis_h[j] = 0;
+            tf_h[j] = 0;
+            if (q < 6 * FACE) {
+                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+                const int ax = f >> 1;
+                const bool plus = f & 1;
+                int c0, c1, c2;
+                face_cell<E>(f, u, w, c0, c1, c2);
+                const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
+                const int32_t tna = ax == 0 ? P.t0 : ax == 1 ? P.t1 : P.t2;
+                if (plus ? tca + 1 < tna : tca > 0) {
+                    const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+                    const uint32_t tnb = plus ? t + ts : t - ts;
+                    const int n0c = ax == 0 ? (plus ? 0 : E - 1) : c0;
+                    const int n1c = ax == 1 ? (plus ? 0 : E - 1) : c1;
+                    const int n2c = ax == 2 ? (plus ? 0 : E - 1) : c2;
+                    vis_h[j] = P.visit[tnb];
+                    tf_h[j] = P.tflags[tnb];
+                    vh[j] = ax == 2 ? P.Zf[((size_t)tnb * 2 + (plus ? 0 : 1)) * FACE + n0c * E + n1c]
+                                    : Tt[(size_t)tnb * V + (n0c * E + n1c) * E + n2c];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CF; j++) {
+            const int q = lane + 64 * (j0 + j);
+            if (q < 6 * FACE) {
+                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+                const int ax = f >> 1;
+                const bool plus = f & 1;
+                int c0, c1, c2;
+                face_cell<E>(f, u, w, c0, c1, c2);
+                double v = FMM_INF;
+                uint8_t fl = 0;
+                if (vis_h[j] != 0 && vis_h[j] <= phase) v = vh[j];
+                if (tf_h[j] & TF_SEED) {
+                    // rare: the neighbour holds seeds; fetch its seed bit
+                    const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+                    const uint32_t tnb = plus ? t + ts : t - ts;
+                    const int n0c = ax == 0 ? (plus ? 0 : E - 1) : c0;
+                    const int n1c = ax == 1 ? (plus ? 0 : E - 1) : c1;
+                    const int n2c = ax == 2 ? (plus ? 0 : E - 1) : c2;
+                    const int pn = (n0c * E + n1c) * E + n2c;
+                    if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
+                }
+                const int d = G::dom(c0, c1, c2);
+                L.T[d] = v;
+                L.fl[d] = fl;
+            }
+        }
+    }
+    if (lane < 12) L.bm[lane] = bits_of(FMM_INF);
     wave_sync();
 
     // ---- ordered relaxation.  Sources at level th are the seeds and the
@@ -632,23 +715,44 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
     PROF_CLOCK(t_levels);
     ws.n_round += (unsigned long long)rounds;
     ws.n_march++;
+    PROF_ADD(10 + mode, 1);
 
-    // ---- write back changed interior points; collect changed faces
-    uint32_t fmask = 0;
+    // ---- write back (every cell on the first write of the tile, else the
+    // changed ones) and classify the changed boundary cells per face: a new
+    // source value is sent at once (the neighbour re-marches, KNOWN_OLD of Alg.
+    // 15), a band value only joins the neighbour's pending minimum (BAND_OLD).
+    uint32_t fsrc = 0, fany = 0;
     for (int p = lane; p < V; p += 64) {
         const int d = G::domp(p);
-        if (L.fl[d] & FL_CHG) {
-            const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
-            const int64_t g = (o0 + i0) * n12 + (o1 + i1) * P.n2 + (o2 + i2);
-            Tg[g] = L.T[d];
-            fmask |= (i0 == 0 ? 1u : 0u) | (i0 == E - 1 ? 2u : 0u) | (i1 == 0 ? 4u : 0u) |
-                     (i1 == E - 1 ? 8u : 0u) | (i2 == 0 ? 16u : 0u) | (i2 == E - 1 ? 32u : 0u);
+        const bool chg = (L.fl[d] & FL_CHG) != 0;
+        if (!(chg || fresh)) continue;
+        const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
+        const double v = L.T[d];
+        Tt[tbase + p] = v;
+        if (i2 == 0) P.Zf[((size_t)t * 2 + 0) * FACE + i0 * E + i1] = v;
+        if (i2 == E - 1) P.Zf[((size_t)t * 2 + 1) * FACE + i0 * E + i1] = v;
+        if (!chg) continue;
+        const uint32_t fm = (i0 == 0 ? 1u : 0u) | (i0 == E - 1 ? 2u : 0u) | (i1 == 0 ? 4u : 0u) |
+                            (i1 == E - 1 ? 8u : 0u) | (i2 == 0 ? 16u : 0u) | (i2 == E - 1 ? 32u : 0u);
+        if (!fm) continue;
+        fany |= fm;
+        if (is_source(v, 0, bnd)) {
+            fsrc |= fm;
+        } else {
+            const int sd = v < 0.0 ? 0 : 1;
+            const unsigned long long b = bits_of(fabs(v));
+            for (int f = 0; f < 6; f++)
+                if ((fm >> f) & 1u) atomicMin(&L.bm[f * 2 + sd], b);
         }
     }
-    uint32_t faces = 0;
+    uint32_t srcFaces = 0, anyFaces = 0;
 #pragma unroll
-    for (int f = 0; f < 6; f++)
-        if (__ballot((fmask >> f) & 1u)) faces |= 1u << f;
+    for (int f = 0; f < 6; f++) {
+        if (__ballot((fsrc >> f) & 1u)) srcFaces |= 1u << f;
+        if (__ballot((fany >> f) & 1u)) anyFaces |= 1u << f;
+    }
+    wave_sync();
+    if (fresh && lane == 0) __hip_atomic_store(&P.visit[t], phase + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     if (lane == 0) {
         TileMeta m;
@@ -661,36 +765,62 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
     ws.gmin0 = fmin(ws.gmin0, tm0);
     ws.gmin1 = fmin(ws.gmin1, tm1);
 
-    // ---- flag neighbours whose halo changed (the overlap exchange)
-    for (int f = 0; f < 6; f++) {
-        if (!((faces >> f) & 1u)) continue;
-        const int ax = f >> 1;
-        const bool plus = f & 1;
-        const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
-        const int32_t tna = ax == 0 ? P.t0 : ax == 1 ? P.t1 : P.t2;
-        if (plus ? tca + 1 >= tna : tca == 0) continue;
-        const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
-        const uint32_t u = plus ? t + ts : t - ts;
-        uint32_t old = 0;
-        if (lane == 0) old = atomicOr(&dprod[u], 1u << (f ^ 1));
-        old = bcast0(old);
-        if (old != 0) continue;
-        if (mode == MODE_M1) {
-            stage_push(L.stD, ws.nD, u, cntD, dlist);
-        } else {
-            ws.pending++;
-            uint32_t oe = 0;
-            if (lane == 0) oe = atomicExch(&P.epoch[u], epoch);
-            oe = bcast0(oe);
-            if (oe != epoch) stage_push(L.stL, ws.nL, u, cntNext, listNext);
+    // ---- pass changed boundary values to the neighbours (Alg. 13-15).  Lane
+    // f < 6 handles face f and lane 6 the tile itself, so the atomics of all
+    // faces are in flight together.
+    {
+        uint32_t u = 0;
+        bool have = false, src = false;
+        if (lane < 6 && ((anyFaces >> lane) & 1u)) {
+            const int f = lane, ax = f >> 1;
+            const bool plus = f & 1;
+            const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
+            const int32_t tna = ax == 0 ? P.t0 : ax == 1 ? P.t1 : P.t2;
+            if (plus ? tca + 1 < tna : tca > 0) {
+                const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+                u = plus ? t + ts : t - ts;
+                have = true;
+                src = (srcFaces >> f) & 1u;
+            }
         }
-    }
-    // ---- keep the tile in the next restart's list while it has a band
-    if (tm0 < FMM_INF || tm1 < FMM_INF) {
-        uint32_t oe = 0;
-        if (lane == 0) oe = atomicExch(&P.epoch[t], epoch);
-        oe = bcast0(oe);
-        if (oe != epoch) stage_push(L.stL, ws.nL, t, cntNext, listNext);
+        const bool self = lane == 6 && (tm0 < FMM_INF || tm1 < FMM_INF);
+        bool toD = false, live = self;
+        if (self) u = t;
+        if (have && src) {
+            // a new source value crossed the face: the neighbour re-marches
+            const uint32_t old = atomicOr(&dprod[u], 1u << (lane ^ 1));
+            if (old == 0) {
+                if (second)
+                    toD = true;
+                else
+                    live = true;
+            }
+        } else if (have) {
+            // only band values: they join the neighbour's pending minimum
+            const unsigned long long b0 = L.bm[lane * 2], b1 = L.bm[lane * 2 + 1];
+            unsigned long long *ux = P.text + ((size_t)u * 3 + phase % 3u) * 2;
+            if (b0 != bits_of(FMM_INF)) atomicMin(&ux[0], b0);
+            if (b1 != bits_of(FMM_INF)) atomicMin(&ux[1], b1);
+            live = true;
+        }
+        bool append = false;
+        if (live) append = atomicExch(&P.epoch[u], epoch) != epoch;
+        // wave-uniform follow-up
+        const unsigned long long mD = __ballot(toD), mL = __ballot(append);
+        const unsigned long long mP = __ballot(have && src && live);
+        ws.pending += (uint32_t)__popcll(mP);
+        for (int f = 0; f < 6; f++) {
+            if (!((anyFaces >> f) & 1u) || ((srcFaces >> f) & 1u)) continue;
+            ws.gmin0 = fmin(ws.gmin0, bitsd(L.bm[f * 2]));
+            ws.gmin1 = fmin(ws.gmin1, bitsd(L.bm[f * 2 + 1]));
+        }
+        for (int k = 0; k < 7; k++) {
+            const uint32_t uk = __shfl(u, k);
+            if ((mD >> k) & 1ull) stage_push(L.stD, ws.nD, uk, cntD, dlist);
+            if ((mL >> k) & 1ull) stage_push(L.stL, ws.nL, uk, cntNext, listNext);
+        }
+        PROF_ADD(13, __popcll(__ballot(have && src)));
+        PROF_ADD(14, __popcll(__ballot(have && !src)));
     }
     wave_sync();
     PROF_CLOCK(t_end);
@@ -702,7 +832,8 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
 
 template <int E, int NW, typename FT>
 __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
-                          const uint32_t *items, uint32_t nitems, const double bnd[2], WaveState &ws)
+                                          uint32_t phase, const uint32_t *items, uint32_t nitems, const double bnd[2],
+                                          WaveState &ws)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Ctrl *c = P.ctrl;
@@ -710,8 +841,13 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
     Slot &nxt = c->slot[(r + 1) % 3];
     uint32_t *listNext = ((r + 1) & 1) ? P.list1 : P.list0;
     const uint32_t epoch = r + 1;
-    uint32_t *dcons = mode == MODE_M1 ? P.dirty0 : P.dirty1;
-    uint32_t *dprod = mode == MODE_M1 ? P.dirty1 : P.dirty0;
+    // flags raised in phase p are read in phase p + 1: dirty[p % 2] is written,
+    // dirty[(p + 1) % 2] (raised in the previous phase) is consumed
+    uint32_t *dcons = (phase & 1u) ? P.dirty0 : P.dirty1;
+    uint32_t *dprod = (phase & 1u) ? P.dirty1 : P.dirty0;
+    // with a second march, tiles flagged by march-1 are handled in it;
+    // otherwise they carry over to the next restart
+    const bool second = mode == MODE_M1 && P.two_march;
     const uint32_t gw = blockIdx.x * NW + wid, GW = gridDim.x * NW;
     PROF_CLOCK(t_phase0);
 
@@ -726,13 +862,20 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             const TileMeta m = P.meta[t];
             lastb[0] = m.lastb[0];
             lastb[1] = m.lastb[1];
-            const bool due = dbits != 0 || (m.tmin[0] < FMM_INF && m.tmin[0] <= bnd[0]) ||
-                             (m.tmin[1] < FMM_INF && m.tmin[1] <= bnd[1]);
+            // pending minimum: the tile's own, and band values its neighbours
+            // have passed on since (Alg. 15, BAND_OLD), one slot per phase
+            unsigned long long *tx = P.text + (size_t)t * 6;
+            unsigned long long xb[6];
+#pragma unroll
+            for (int k = 0; k < 6; k++) xb[k] = ld_acq64(&tx[k]);
+            const double p0 = fmin(m.tmin[0], fmin(bitsd(xb[0]), fmin(bitsd(xb[2]), bitsd(xb[4]))));
+            const double p1 = fmin(m.tmin[1], fmin(bitsd(xb[1]), fmin(bitsd(xb[3]), bitsd(xb[5]))));
+            const bool due = dbits != 0 || (p0 < FMM_INF && p0 <= bnd[0]) || (p1 < FMM_INF && p1 <= bnd[1]);
             if (!due) {
                 // carried over unchanged to the next restart
-                ws.gmin0 = fmin(ws.gmin0, m.tmin[0]);
-                ws.gmin1 = fmin(ws.gmin1, m.tmin[1]);
-                if (m.tmin[0] < FMM_INF || m.tmin[1] < FMM_INF) {
+                ws.gmin0 = fmin(ws.gmin0, p0);
+                ws.gmin1 = fmin(ws.gmin1, p1);
+                if (p0 < FMM_INF || p1 < FMM_INF) {
                     uint32_t oe = 0;
                     if (lane == 0) oe = atomicExch(&P.epoch[t], epoch);
                     oe = bcast0(oe);
@@ -741,9 +884,19 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
                 PROF_ADD(7, 1);
                 continue;
             }
+            // the march reads the whole halo, so the values passed on in earlier
+            // phases (whose data the barrier made visible) are consumed; the
+            // current phase's slot stays for a later march
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 6; k++)
+                    if ((uint32_t)(k >> 1) != phase % 3u && xb[k] != bits_of(FMM_INF))
+                        atomicExch(&tx[k], bits_of(FMM_INF));
+            }
+            wave_sync();
         }
-        tile_march<E, FT>(P, L, t, mode, dbits, bnd, lastb, epoch, ws, listNext, &nxt.live_len, P.dlist,
-                          &cur.d_len, dprod);
+        tile_march<E, FT>(P, L, t, mode, dbits, bnd, lastb, epoch, phase, second, ws, listNext, &nxt.live_len,
+                          P.dlist, &cur.d_len, dprod);
     }
 
     PROF_CLOCK(t_phase1);
@@ -770,8 +923,8 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
         S.baseL = tl ? atomicAdd(&nxt.live_len, tl) : 0u;
         S.baseD = td ? atomicAdd(&cur.d_len, td) : 0u;
         if (tp) atomicAdd(&nxt.pending, tp);
-        if (g0 < FMM_INF) atomicMin(&nxt.gmin[0], dbits(g0));
-        if (g1 < FMM_INF) atomicMin(&nxt.gmin[1], dbits(g1));
+        if (g0 < FMM_INF) atomicMin(&nxt.gmin[0], bits_of(g0));
+        if (g1 < FMM_INF) atomicMin(&nxt.gmin[1], bits_of(g1));
     }
     __syncthreads();
     uint32_t offL = S.baseL, offD = S.baseD;
@@ -813,20 +966,22 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
     // march inlined once.
     int mode = MODE_INIT;
     uint32_t r = 0;
+    uint32_t phase = 1;  // phases are numbered from 1; tile visit stamps refer to them
     double bnd[2] = {-1.0, -1.0};
     const uint32_t *items = P.list0;
     uint32_t nitems = ld_acq(&c->slot[0].live_len);
     bool run = ld_acq(&c->error) == 0;
     while (run) {
         PROF_CLOCK(t_p0);
-        run_phase<E, NW, FT>(P, L, s_g, mode, r, items, nitems, bnd, ws);
+        run_phase<E, NW, FT>(P, L, s_g, mode, r, phase, items, nitems, bnd, ws);
         PROF_CLOCK(t_p1);
         const bool passed = grid_barrier(c, gen, nwg, &s_g.ok);
         PROF_CLOCK(t_p2);
         PROF_ADD(1, t_p2 - t_p0);
         PROF_ADD(9, t_p2 - t_p1);
         if (!passed) break;
-        if (mode == MODE_M1) {
+        phase++;
+        if (mode == MODE_M1 && P.two_march) {
             mode = MODE_M2;
             items = P.dlist;
             nitems = ld_acq(&c->slot[r % 3].d_len);
@@ -839,7 +994,7 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
         const uint32_t len = ld_acq(&S.live_len);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             Slot &Z = c->slot[(r + 2) % 3];
-            Z.gmin[0] = Z.gmin[1] = dbits(FMM_INF);
+            Z.gmin[0] = Z.gmin[1] = bits_of(FMM_INF);
             Z.live_len = Z.pending = Z.d_len = 0;
         }
         // Alg. 16 exit test: both sides have no band value within the width
@@ -897,7 +1052,9 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
 }
 
 // ---------------------------------------------------------------------------
-// Preparation: workspace reset, T = +inf, seeds (Alg. 8), initial tile list.
+// Preparation (Alg. 8): workspace reset, tiled copy of F, seeds and the
+// initial tile list.  Tiles never written hold +inf implicitly (visit = 0), so
+// T is not filled.
 
 __global__ void k_init_ws(Params P, int E)
 {
@@ -913,7 +1070,7 @@ __global__ void k_init_ws(Params P, int E)
         c->nwg = 0;
         c->tile_edge = (uint32_t)E;
         for (int k = 0; k < 3; k++) {
-            c->slot[k].gmin[0] = c->slot[k].gmin[1] = dbits(FMM_INF);
+            c->slot[k].gmin[0] = c->slot[k].gmin[1] = bits_of(FMM_INF);
             c->slot[k].live_len = c->slot[k].pending = c->slot[k].d_len = 0;
         }
         c->n_march = c->n_solve = c->n_round = c->n_reopen = 0;
@@ -930,15 +1087,31 @@ __global__ void k_init_ws(Params P, int E)
         P.dirty1[i] = 0;
         P.epoch[i] = 0;
         P.tflags[i] = 0;
+        P.visit[i] = 0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) P.text[i * 6 + k] = bits_of(FMM_INF);
     }
     const int64_t nm = (int64_t)P.ntiles * P.mask_words;
     for (int64_t i = i0; i < nm; i += stride) P.mask[i] = 0ull;
 }
 
-__global__ void k_fill_inf(double *__restrict__ T, int64_t n)
+// Tiled copy of the speeds: one workgroup per tile, 0 outside the grid.
+template <int E, typename FT> __global__ void k_tile_speed(Params P)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) T[i] = FMM_INF;
+    constexpr int V = E * E * E;
+    const FT *F = (const FT *)P.F;
+    FT *Ft = (FT *)P.Ft;
+    const int64_t n12 = P.n1 * P.n2;
+    for (int64_t t = blockIdx.x; t < (int64_t)P.ntiles; t += gridDim.x) {
+        const int64_t tz = t % P.t2, ty = (t / P.t2) % P.t1, tx = t / ((int64_t)P.t2 * P.t1);
+        for (int p = threadIdx.x; p < V; p += blockDim.x) {
+            const int i0 = p / (E * E), i1 = (p / E) % E, i2 = p % E;
+            const int64_t g0 = tx * E + i0, g1 = ty * E + i1, g2 = tz * E + i2;
+            FT f = (FT)0;
+            if (g0 < P.n0 && g1 < P.n1 && g2 < P.n2) f = F[g0 * n12 + g1 * P.n2 + g2];
+            Ft[(size_t)t * V + p] = f;
+        }
+    }
 }
 
 __device__ __forceinline__ void add_init_tile(const Params &P, uint32_t t)
@@ -950,41 +1123,89 @@ __device__ __forceinline__ void add_init_tile(const Params &P, uint32_t t)
     }
 }
 
-__global__ void k_seeds(Params P, const int64_t *__restrict__ idx, const double *__restrict__ val, int64_t ns, int E)
+// Locate a seed: tile index and interior index, or false if out of range.
+__device__ __forceinline__ bool seed_cell(const Params &P, int64_t g, int E, uint32_t &t, int &p, int l[3],
+                                          int64_t c[3])
 {
     const int64_t N = P.n0 * P.n1 * P.n2;
+    if (g < 0 || g >= N) return false;
+    const int64_t i0 = g / (P.n1 * P.n2), rem = g - i0 * (P.n1 * P.n2);
+    const int64_t i1 = rem / P.n2, i2 = rem - i1 * P.n2;
+    c[0] = i0 / E;
+    c[1] = i1 / E;
+    c[2] = i2 / E;
+    l[0] = (int)(i0 - c[0] * E);
+    l[1] = (int)(i1 - c[1] * E);
+    l[2] = (int)(i2 - c[2] * E);
+    t = (uint32_t)((c[0] * P.t1 + c[1]) * P.t2 + c[2]);
+    p = (l[0] * E + l[1]) * E + l[2];
+    return true;
+}
+
+// Seeds, pass 1: validate, set the seed bits, and list the seed tiles and
+// the neighbours across any tile face a seed lies on.
+__global__ void k_seed_mark(Params P, const int64_t *__restrict__ idx, const double *__restrict__ val, int64_t ns,
+                            int E)
+{
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = idx[k];
-        const double v = val[k];
-        if (g < 0 || g >= N) {
+        uint32_t t;
+        int p, l[3];
+        int64_t c[3];
+        if (!seed_cell(P, idx[k], E, t, p, l, c)) {
             atomicOr(&P.ctrl->error, ERR_SEED_RANGE);
             continue;
         }
-        if (!(fabs(v) < FMM_INF)) {
+        if (!(fabs(val[k]) < FMM_INF)) {
             atomicOr(&P.ctrl->error, ERR_SEED_VALUE);
             continue;
         }
-        const int64_t i0 = g / (P.n1 * P.n2), rem = g - i0 * (P.n1 * P.n2);
-        const int64_t i1 = rem / P.n2, i2 = rem - i1 * P.n2;
-        const int64_t c[3] = {i0 / E, i1 / E, i2 / E};
-        const int l[3] = {(int)(i0 - c[0] * E), (int)(i1 - c[1] * E), (int)(i2 - c[2] * E)};
-        const uint32_t ts[3] = {(uint32_t)P.t1 * (uint32_t)P.t2, (uint32_t)P.t2, 1u};
-        const int32_t tn[3] = {P.t0, P.t1, P.t2};
-        const uint32_t t = (uint32_t)((c[0] * P.t1 + c[1]) * P.t2 + c[2]);
-        const int p = (l[0] * E + l[1]) * E + l[2];
         const unsigned long long bit = 1ull << (p & 63);
         const unsigned long long old = atomicOr(&P.mask[(size_t)t * P.mask_words + (p >> 6)], bit);
         if (old & bit) {
             atomicOr(&P.ctrl->error, ERR_SEED_DUP);
             continue;
         }
-        P.T[g] = v;
         atomicOr(&P.tflags[t], (uint32_t)TF_SEED);
         add_init_tile(P, t);
+        const uint32_t ts[3] = {(uint32_t)P.t1 * (uint32_t)P.t2, (uint32_t)P.t2, 1u};
+        const int32_t tn[3] = {P.t0, P.t1, P.t2};
+#pragma unroll
         for (int ax = 0; ax < 3; ax++) {
             if (l[ax] == 0 && c[ax] > 0) add_init_tile(P, t - ts[ax]);
             if (l[ax] == E - 1 && c[ax] + 1 < tn[ax]) add_init_tile(P, t + ts[ax]);
         }
+    }
+}
+
+// Seeds, pass 2: every seed tile starts as +inf (tiled T and face buffer).
+template <int E> __global__ void k_seed_fill(Params P)
+{
+    constexpr int V = E * E * E, FACE = E * E;
+    const uint32_t n = P.ctrl->slot[0].live_len;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const uint32_t t = P.list0[i];
+        if (!(P.tflags[t] & TF_SEED)) continue;
+        for (int p = threadIdx.x; p < V; p += blockDim.x) P.Tt[(size_t)t * V + p] = FMM_INF;
+        for (int p = threadIdx.x; p < 2 * FACE; p += blockDim.x) P.Zf[(size_t)t * 2 * FACE + p] = FMM_INF;
+        if (threadIdx.x == 0) P.visit[t] = 1u;
+    }
+}
+
+// Seeds, pass 3: the values (KNOWN_FIX points of Alg. 8).
+__global__ void k_seed_scatter(Params P, const int64_t *__restrict__ idx, const double *__restrict__ val, int64_t ns,
+                               int E)
+{
+    if (P.ctrl->error) return;
+    const int V = E * E * E, FACE = E * E;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t t;
+        int p, l[3];
+        int64_t c[3];
+        if (!seed_cell(P, idx[k], E, t, p, l, c)) continue;
+        const double v = val[k];
+        P.Tt[(size_t)t * V + p] = v;
+        if (l[2] == 0) P.Zf[((size_t)t * 2 + 0) * FACE + l[0] * E + l[1]] = v;
+        if (l[2] == E - 1) P.Zf[((size_t)t * 2 + 1) * FACE + l[0] * E + l[1]] = v;
     }
 }
 
@@ -999,10 +1220,13 @@ template <typename FT> __global__ void k_validate(Params P)
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: status bytes, +inf for points outside the band, statistics.
+// Finalize: row-major T (accepted points and seeds keep their values, all
+// others +inf), status bytes and statistics.  One workgroup handles a run of
+// E points along axis 2, i.e. one row of one tile, per thread group.
 
-__global__ void k_finalize(Params P, uint8_t *__restrict__ status, int E)
+template <int E> __global__ void k_finalize(Params P, uint8_t *__restrict__ status)
 {
+    constexpr int V = E * E * E;
     const int64_t rows = P.n0 * P.n1;
     const int64_t chunks = (P.n2 + blockDim.x - 1) / blockDim.x;
     unsigned long long acc = 0;
@@ -1014,33 +1238,33 @@ __global__ void k_finalize(Params P, uint8_t *__restrict__ status, int E)
         const int64_t i0 = row / P.n1, i1 = row - i0 * P.n1;
         const int64_t g = row * P.n2 + i2;
         const uint32_t t = (uint32_t)(((i0 / E) * P.t1 + i1 / E) * P.t2 + i2 / E);
+        const int p = (int)(((i0 % E) * E + i1 % E) * E + i2 % E);
         bool seed = false;
-        if (P.tflags[t] & TF_SEED) {
-            const int p = (int)(((i0 % E) * E + i1 % E) * E + i2 % E);
-            seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
-        }
-        const double v = P.T[g];
+        if (P.tflags[t] & TF_SEED) seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
+        const double v = P.visit[t] ? P.Tt[(size_t)t * V + p] : FMM_INF;
         const double a = fabs(v);
         const uint8_t neg = v < 0.0 ? 0x80 : 0;
         uint8_t st;
+        double out = FMM_INF;
         if (seed) {
             st = 3 | neg;
+            out = v;
             mx = fmax(mx, a);
         } else if (a < FMM_INF && a <= P.width) {
             st = 2 | neg;
+            out = v;
             acc++;
             mx = fmax(mx, a);
         } else if (a < FMM_INF) {
             st = 1 | neg;
-            P.T[g] = FMM_INF;
         } else {
             st = 0;
         }
+        P.T[g] = out;
         if (status) status[g] = st;
     }
-    // block reduction
-    __shared__ unsigned long long s_acc[32];
-    __shared__ double s_mx[32];
+    __shared__ unsigned long long s_acc[16];
+    __shared__ double s_mx[16];
     acc = wave_sum(acc);
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1057,7 +1281,7 @@ __global__ void k_finalize(Params P, uint8_t *__restrict__ status, int E)
             m = fmax(m, s_mx[w]);
         }
         if (a) atomicAdd(&P.ctrl->n_accepted, a);
-        atomicMax(&P.ctrl->max_abs_bits, dbits(m));
+        atomicMax(&P.ctrl->max_abs_bits, bits_of(m));
     }
 }
 
@@ -1075,18 +1299,26 @@ static int num_cus()
     return cus;
 }
 
-hipError_t launch_prepare(const Params &P, const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, int E,
-                          bool validate, bool f64, hipStream_t s)
+template <int E> static hipError_t launch_prepare_t(const Params &P, const int64_t *seed_idx, const double *seed_val,
+                                                   int64_t n_seeds, bool validate, bool f64, hipStream_t s)
 {
     const int cus = num_cus();
     hipLaunchKernelGGL(k_init_ws, dim3(cus * 4), dim3(256), 0, s, P, E);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_inf, dim3(cus * 16), dim3(256), 0, s, P.T, P.n0 * P.n1 * P.n2);
+    const unsigned tb = (unsigned)std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * 32);
+    if (f64)
+        hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(256), 0, s, P);
+    else
+        hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(256), 0, s, P);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n_seeds > 0) {
-        const int64_t blocks = std::min<int64_t>((n_seeds + 255) / 256, (int64_t)cus * 16);
-        hipLaunchKernelGGL(k_seeds, dim3((unsigned)blocks), dim3(256), 0, s, P, seed_idx, seed_val, n_seeds, E);
+        const unsigned blocks = (unsigned)std::min<int64_t>((n_seeds + 255) / 256, (int64_t)cus * 16);
+        hipLaunchKernelGGL(k_seed_mark, dim3(blocks), dim3(256), 0, s, P, seed_idx, seed_val, n_seeds, E);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_seed_fill<E>, dim3(cus * 8), dim3(256), 0, s, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_seed_scatter, dim3(blocks), dim3(256), 0, s, P, seed_idx, seed_val, n_seeds, E);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (validate) {
@@ -1097,6 +1329,17 @@ hipError_t launch_prepare(const Params &P, const int64_t *seed_idx, const double
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_prepare(const Params &P, const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, int E,
+                          bool validate, bool f64, hipStream_t s)
+{
+    switch (E) {
+    case 4: return launch_prepare_t<4>(P, seed_idx, seed_val, n_seeds, validate, f64, s);
+    case 8: return launch_prepare_t<8>(P, seed_idx, seed_val, n_seeds, validate, f64, s);
+    case 16: return launch_prepare_t<16>(P, seed_idx, seed_val, n_seeds, validate, f64, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_out)
@@ -1120,8 +1363,10 @@ template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Pa
 hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
 {
     switch (E) {
-    case 4: return f64 ? launch_driver_t<4, 8, double>(P, s, nwg_out) : launch_driver_t<4, 8, float>(P, s, nwg_out);
-    case 8: return f64 ? launch_driver_t<8, 8, double>(P, s, nwg_out) : launch_driver_t<8, 8, float>(P, s, nwg_out);
+    case 4: return f64 ? launch_driver_t<4, 12, double>(P, s, nwg_out) : launch_driver_t<4, 12, float>(P, s, nwg_out);
+    case 8:
+        return f64 ? launch_driver_t<8, FMM_E8_WAVES_F64, double>(P, s, nwg_out)
+                   : launch_driver_t<8, FMM_E8_WAVES_F32, float>(P, s, nwg_out);
     case 16: return f64 ? launch_driver_t<16, 1, double>(P, s, nwg_out) : launch_driver_t<16, 1, float>(P, s, nwg_out);
     default: return hipErrorInvalidValue;
     }
@@ -1130,7 +1375,12 @@ hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32
 hipError_t launch_finalize(const Params &P, int E, uint8_t *status, hipStream_t s)
 {
     const int cus = num_cus();
-    hipLaunchKernelGGL(k_finalize, dim3(cus * 16), dim3(256), 0, s, P, status, E);
+    switch (E) {
+    case 4: hipLaunchKernelGGL(k_finalize<4>, dim3(cus * 16), dim3(256), 0, s, P, status); break;
+    case 8: hipLaunchKernelGGL(k_finalize<8>, dim3(cus * 16), dim3(256), 0, s, P, status); break;
+    case 16: hipLaunchKernelGGL(k_finalize<16>, dim3(cus * 16), dim3(256), 0, s, P, status); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

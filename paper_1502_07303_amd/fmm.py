@@ -20,6 +20,7 @@ FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_EDEVICE = 0, -1, -2, 
 FMM_F32, FMM_F64 = 0, 1
 FMM_VALIDATE = 1
 FMM_TIMING = 2
+FMM_ONE_MARCH = 4
 
 DERR = {1: "seed index out of range", 2: "duplicate seed", 4: "non-finite seed value",
         8: "non-finite speed", 16: "restart limit", 32: "barrier timeout", 64: "round cap",
@@ -67,7 +68,7 @@ def load_library(path: str = LIB_PATH):
     P, i64, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
     lib.fmm_default_opts.argtypes = [ctypes.POINTER(FmmOpts)]
     lib.fmm_default_opts.restype = None
-    lib.fmm_workspace_bytes.argtypes = [i64, i64, i64, i64, ctypes.POINTER(FmmOpts)]
+    lib.fmm_workspace_bytes.argtypes = [i64, i64, i64, i64, ctypes.c_int, ctypes.POINTER(FmmOpts)]
     lib.fmm_workspace_bytes.restype = ctypes.c_size_t
     lib.fmm_solve.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, i64, ctypes.POINTER(FmmOpts),
                               P, P, P, ctypes.c_size_t, P]
@@ -87,7 +88,7 @@ def strerror(code: int) -> str:
 
 
 def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, validate=False,
-              time_limit_s=0, timing=False, inner_stride=None) -> FmmOpts:
+              time_limit_s=0, timing=False, inner_stride=None, one_march=False) -> FmmOpts:
     o = FmmOpts()
     load_library().fmm_default_opts(ctypes.byref(o))
     o.band_width = float(band_width)
@@ -95,14 +96,15 @@ def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, val
     o.inner_stride = 0.0 if inner_stride is None else float(inner_stride)
     o.tile_edge = int(tile_edge)
     o.max_restarts = int(max_restarts)
-    o.flags = (FMM_VALIDATE if validate else 0) | (FMM_TIMING if timing else 0)
+    o.flags = (FMM_VALIDATE if validate else 0) | (FMM_TIMING if timing else 0) | (FMM_ONE_MARCH if one_march else 0)
     o.time_limit_s = int(time_limit_s)
     return o
 
 
-def workspace_bytes(shape, n_seeds, opts: Optional[FmmOpts] = None) -> int:
+def workspace_bytes(shape, n_seeds, opts: Optional[FmmOpts] = None, f_dtype=FMM_F64) -> int:
     n0, n1, n2 = shape
-    return int(load_library().fmm_workspace_bytes(n0, n1, n2, n_seeds, ctypes.byref(opts) if opts else None))
+    return int(load_library().fmm_workspace_bytes(n0, n1, n2, n_seeds, int(f_dtype),
+                                                  ctypes.byref(opts) if opts else None))
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -119,13 +121,18 @@ class Solver:
     option set, so repeated solves allocate nothing."""
 
     def __init__(self, shape, n_seeds, h, band_width=math.inf, stride=None, tile_edge=0, max_restarts=0,
-                 validate=False, device="cuda", time_limit_s=0, timing=False, inner_stride=None):
+                 validate=False, device="cuda", time_limit_s=0, timing=False, inner_stride=None,
+                 speed_dtype=torch.float64, one_march=False):
         self.lib = load_library()
         self.shape = tuple(int(x) for x in shape)
         self.h = float(h)
         self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s, timing,
-                              inner_stride)
-        nbytes = workspace_bytes(self.shape, n_seeds, self.opts)
+                              inner_stride, one_march)
+        if speed_dtype not in (torch.float32, torch.float64):
+            raise FmmError(FMM_EINVAL, f"unsupported speed dtype {speed_dtype}")
+        self.speed_dtype = speed_dtype
+        nbytes = workspace_bytes(self.shape, n_seeds, self.opts,
+                                 FMM_F32 if speed_dtype == torch.float32 else FMM_F64)
         if nbytes == 0:
             raise FmmError(FMM_EINVAL, "invalid problem or options")
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
@@ -142,6 +149,8 @@ class Solver:
             dt = FMM_F64
         else:
             raise FmmError(FMM_EINVAL, f"unsupported speed dtype {F.dtype}")
+        if F.dtype != self.speed_dtype:
+            raise FmmError(FMM_EINVAL, f"solver was sized for {self.speed_dtype} speeds, got {F.dtype}")
         if tuple(F.shape) != self.shape or not F.is_contiguous() or not F.is_cuda:
             raise FmmError(FMM_EINVAL, "F must be a contiguous CUDA tensor of the solver's shape")
         if seed_idx.dtype != torch.int64 or seed_val.dtype != torch.float64:
@@ -173,10 +182,10 @@ class Solver:
 
 def solve(F: torch.Tensor, h: float, seed_idx: torch.Tensor, seed_val: torch.Tensor, band_width=math.inf,
           stride=None, tile_edge=0, max_restarts=0, validate=False, with_status=True, check=True,
-          time_limit_s=0, inner_stride=None):
+          time_limit_s=0, inner_stride=None, one_march=False):
     """One solve on F's device; returns (T, status, stats) after synchronising."""
     s = Solver(F.shape, seed_idx.numel(), h, band_width, stride, tile_edge, max_restarts, validate, F.device,
-               time_limit_s, inner_stride=inner_stride)
+               time_limit_s, inner_stride=inner_stride, speed_dtype=F.dtype, one_march=one_march)
     T = torch.empty(F.shape, dtype=torch.float64, device=F.device)
     status = torch.empty(F.shape, dtype=torch.uint8, device=F.device) if with_status else None
     s.solve_into(F, seed_idx, seed_val, T, status)

@@ -60,21 +60,24 @@ def test_default_opts(fmm):
 
 def test_workspace_bytes(fmm):
     lib = fmm.load_library()
-    w8 = lib.fmm_workspace_bytes(64, 64, 64, 1, None)
+    F64, F32 = fmm.FMM_F64, fmm.FMM_F32
+    w8 = lib.fmm_workspace_bytes(64, 64, 64, 1, F64, None)
     assert w8 > 0 and w8 % 256 == 0
+    assert lib.fmm_workspace_bytes(64, 64, 64, 1, F32, None) < w8  # FP32 tiled speeds
     o = fmm.make_opts(tile_edge=4)
-    w4 = lib.fmm_workspace_bytes(64, 64, 64, 1, ctypes.byref(o))
-    assert w4 > w8  # more tiles
+    w4 = lib.fmm_workspace_bytes(64, 64, 64, 1, F64, ctypes.byref(o))
+    assert w4 > w8  # more tiles, more bookkeeping
     # ragged grids round up to whole tiles
-    assert lib.fmm_workspace_bytes(65, 64, 64, 1, None) > w8
+    assert lib.fmm_workspace_bytes(65, 64, 64, 1, F64, None) > w8
     # invalid
-    assert lib.fmm_workspace_bytes(0, 64, 64, 1, None) == 0
-    assert lib.fmm_workspace_bytes(64, 64, 64, -1, None) == 0
+    assert lib.fmm_workspace_bytes(0, 64, 64, 1, F64, None) == 0
+    assert lib.fmm_workspace_bytes(64, 64, 64, -1, F64, None) == 0
+    assert lib.fmm_workspace_bytes(64, 64, 64, 1, 9, None) == 0
     bad = fmm.make_opts(tile_edge=5)
-    assert lib.fmm_workspace_bytes(64, 64, 64, 1, ctypes.byref(bad)) == 0
-    # 1024^3 with 8^3 tiles stays modest next to the grid arrays
-    big = lib.fmm_workspace_bytes(1024, 1024, 1024, 4, None)
-    assert 0 < big < 400 * 2 ** 20
+    assert lib.fmm_workspace_bytes(64, 64, 64, 1, F64, ctypes.byref(bad)) == 0
+    # 1024^3 FP32: tiled T (8 B) + tiled F (4 B) + axis-2 faces (2 B) per point + bookkeeping
+    big = lib.fmm_workspace_bytes(1024, 1024, 1024, 4, F32, None)
+    assert 14 * 2 ** 30 < big < 15 * 2 ** 30
 
 
 def _call(fmm, **kw):

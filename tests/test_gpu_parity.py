@@ -182,3 +182,18 @@ def test_restart_limit(fmm):
     with pytest.raises(fmm.FmmError) as ei:
         fmm.solve(w.F.to(dev), w.h, w.seed_idx.to(dev), w.seed_val.to(dev), max_restarts=1, time_limit_s=30)
     assert ei.value.code == fmm.FMM_ENOCONV
+
+
+@pytest.mark.parametrize("shape,seed", [((37, 29, 45), 1), ((33, 40, 18), 2)])
+def test_one_march_per_restart_parity(fmm, oracle_mod, shape, seed):
+    """FMM_ONE_MARCH defers the second march of Alg. 16 to the next restart;
+    the solution must not change."""
+    w = inputs.random_small(shape, n_sources=2, seed=seed, zero_frac=0.05)
+    To, so, _ = oracle_solve(oracle_mod, w)
+    for stride_h in (0.5, 2.0, math.inf):
+        Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, one_march=True)
+        assert_parity(Tg, sg, To, so)
+    w2 = inputs.spheres(n=40, n_spheres=4, seed=3, width=0.12)
+    To, so, _ = oracle_solve(oracle_mod, w2)
+    Tg, sg, st = gpu_solve(fmm, w2, one_march=True)
+    assert_parity(Tg, sg, To, so, allow_edge=w2.width)
