@@ -159,7 +159,6 @@ template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int 
 #endif
 
 constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
-constexpr int KR = 2;      // candidates per lane held in registers per relaxation step
 constexpr int MAX_ROUNDS = 1 << 16;
 
 enum : uint8_t { FL_SEED = 1, FL_UPD = 2, FL_CHG = 4 };
@@ -346,25 +345,33 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 }
 
 // Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
-// new signed value if it improves on the current one.
+// new signed value if it improves on the current one.  Also hands back what
+// the update step needs without another LDS round trip: the old value, the
+// magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z) and which of them
+// are updatable interior cells.
 template <int E, typename FT>
-__device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, double h, const double bnd[2], double &out)
+__device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, double h, const double bnd[2], double &out,
+                                           double &vp, double na[6], uint32_t &upd)
 {
     using G = Geo<E>;
     const int d = G::domp(p);
-    const double vp = L.T[d];
+    vp = L.T[d];
     const double ap = fabs(vp);
     double am[3], ap3[3];  // per-axis minima for side - and side +
+    upd = 0;
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
         const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
         double mneg = FMM_INF, mpos = FMM_INF;
 #pragma unroll
-        for (int s = -1; s <= 1; s += 2) {
-            const int dn = d + s * off;
+        for (int s = 0; s < 2; s++) {
+            const int dn = s ? d + off : d - off;
             const double v = L.T[dn];
+            const uint8_t fl = L.fl[dn];
             const double a = fabs(v);
-            if (a < ap && is_source(v, L.fl[dn], bnd)) {
+            na[2 * ax + s] = a;
+            upd |= (fl & FL_UPD) ? (1u << (2 * ax + s)) : 0u;
+            if (a < ap && is_source(v, fl, bnd)) {
                 if (v < 0.0)
                     mneg = fmin(mneg, a);
                 else
@@ -398,9 +405,13 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, doubl
     return improved;
 }
 
-// Jacobi relaxation at level th until no candidate improves; returns the
-// number of rounds.  Every evaluation of a round reads the values of the
-// previous round, so the result does not depend on lane order.
+// Relaxation at level th until no candidate improves; returns the number of
+// rounds.  Candidates are taken 64 at a time: all evaluations of a chunk read
+// before any of its writes, later chunks see earlier ones (the list order is
+// fixed, so the result is deterministic, and the fixed point is the same).
+// Neighbours are marked from the magnitudes the evaluation read; values only
+// decrease, so a neighbour lowered meanwhile is at worst marked needlessly,
+// never missed.
 template <int E, typename FT>
 __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, const double th[2], const double lastb[2],
                                      WaveState &ws)
@@ -415,31 +426,31 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, const d
             if (lane == 0) atomicOr(&P.ctrl->error_run, ERR_ROUNDS);
             break;
         }
-        for (int base = 0; base < n; base += 64 * KR) {
-            double nv[KR];
-            bool ch[KR];
-#pragma unroll
-            for (int j = 0; j < KR; j++) {
-                const int k = base + lane + 64 * j;
-                ch[j] = false;
-                nv[j] = 0.0;
-                if (k < n) {
-                    ch[j] = eval_point(L, (int)L.list[cur][k], P.h, th, nv[j]);
-                    ws.n_solve++;
-                }
+        for (int base = 0; base < n; base += 64) {
+            const int k = base + lane;
+            double nv = 0.0, vp = 0.0, na[6];
+            uint32_t upd = 0;
+            bool ch = false;
+            int p = 0;
+            if (k < n) {
+                p = L.list[cur][k];
+                ch = eval_point(L, p, P.h, th, nv, vp, na, upd);
+                ws.n_solve++;
             }
             wave_sync();
-#pragma unroll
-            for (int j = 0; j < KR; j++) {
-                const int k = base + lane + 64 * j;
-                if (k < n && ch[j]) {
-                    const int p = L.list[cur][k];
-                    const int d = G::domp(p);
-                    const double old = L.T[d];
-                    if (is_source(old, 0, th) || fabs(old) <= (old < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
-                    L.T[d] = nv[j];
-                    L.fl[d] |= FL_CHG;
-                    if (is_source(nv[j], 0, th)) mark_nbrs(L, p, d, fabs(nv[j]));
+            if (ch) {
+                const int d = G::domp(p);
+                if (is_source(vp, 0, th) || fabs(vp) <= (vp < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
+                L.T[d] = nv;
+                L.fl[d] |= FL_CHG;
+                const double a = fabs(nv);
+                if (is_source(nv, 0, th)) {
+                    if (((upd >> 0) & 1u) && na[0] > a) L.cf[p - E * E] = 1;
+                    if (((upd >> 1) & 1u) && na[1] > a) L.cf[p + E * E] = 1;
+                    if (((upd >> 2) & 1u) && na[2] > a) L.cf[p - E] = 1;
+                    if (((upd >> 3) & 1u) && na[3] > a) L.cf[p + E] = 1;
+                    if (((upd >> 4) & 1u) && na[4] > a) L.cf[p - 1] = 1;
+                    if (((upd >> 5) & 1u) && na[5] > a) L.cf[p + 1] = 1;
                 }
             }
             wave_sync();
