@@ -18,6 +18,8 @@ struct alignas(128) Slot {
     uint32_t pad[25];
 };
 
+constexpr int WORK_SEGS = 8;  // item-list segments, one per XCD
+
 struct Ctrl {
     alignas(128) uint32_t bar;  // grid barrier arrivals (monotonic)
     alignas(128) uint32_t abort;
@@ -35,6 +37,9 @@ struct Ctrl {
     unsigned long long max_abs_bits;
     // cycle counters of builds with FMM_PROFILE defined (zero otherwise)
     alignas(128) unsigned long long prof[16];
+    // work counters of the phase loop: per phase (mod 3) one counter per
+    // segment of the item list, 128 B apart so that each has its own line
+    alignas(128) uint32_t work[3][WORK_SEGS][32];
 };
 
 // Per-tile record: smallest |T| per side among the tile's pending band values

@@ -859,11 +859,33 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
     // with a second march, tiles flagged by march-1 are handled in it;
     // otherwise they carry over to the next restart
     const bool second = mode == MODE_M1 && P.two_march;
-    const uint32_t gw = blockIdx.x * NW + wid, GW = gridDim.x * NW;
     PROF_CLOCK(t_phase0);
+    // The counters of the next phase are cleared now; their last use ended
+    // two barriers ago and the barrier that ends this phase publishes them.
+    if (blockIdx.x == 0 && threadIdx.x < WORK_SEGS) c->work[(phase + 1) % 3][threadIdx.x][0] = 0;
 
-    for (uint32_t i = gw; i < nitems; i += GW) {
+    // Dynamic distribution: the item list is cut into WORK_SEGS segments, one
+    // per XCD (workgroups are dispatched to XCDs round robin), each with its
+    // own counter.  A wavefront claims items of its own segment one at a time
+    // and then helps with the others; the claim for the next item is issued
+    // before the current one is marched so its latency overlaps the loads.
+    uint32_t(*cnt)[32] = c->work[phase % 3];
+    uint32_t seg = blockIdx.x % WORK_SEGS, left = WORK_SEGS;
+    uint32_t claim = 0;
+    if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
+    for (;;) {
+        const uint32_t k = bcast0(claim);
+        const uint32_t lo = (uint32_t)(((uint64_t)nitems * seg) / WORK_SEGS);
+        const uint32_t hi = (uint32_t)(((uint64_t)nitems * (seg + 1)) / WORK_SEGS);
+        if (k >= hi - lo) {
+            if (--left == 0) break;
+            seg = (seg + 1) % WORK_SEGS;
+            if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
+            continue;
+        }
+        if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
         if (ld_acq(&c->abort)) break;
+        const uint32_t i = lo + k;
         const uint32_t t = items[i];
         uint32_t dbits = 0;
         double lastb[2] = {-FMM_INF, -FMM_INF};
@@ -1086,6 +1108,8 @@ __global__ void k_init_ws(Params P, int E)
         }
         c->n_march = c->n_solve = c->n_round = c->n_reopen = 0;
         for (int k = 0; k < 16; k++) c->prof[k] = 0;
+        for (int k = 0; k < 3; k++)
+            for (int g = 0; g < WORK_SEGS; g++) c->work[k][g][0] = 0;
         c->n_accepted = 0;
         c->max_abs_bits = 0;
     }
