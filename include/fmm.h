@@ -89,6 +89,10 @@ typedef struct {
     /* Wall-clock limit of the restart driver in seconds (0 selects 300); a
      * solve that exceeds it stops with FMM_DERR_TIMEOUT. */
     uint32_t time_limit_s;
+    /* Restart stride in units of each problem's own h; a value > 0 takes
+     * precedence over `stride` (useful for a batch whose problems have
+     * different spacings). */
+    double stride_h;
 } fmm_opts;
 
 typedef struct {
@@ -109,7 +113,8 @@ typedef struct {
 } fmm_stats;
 
 /* Fill *opts with the defaults: band_width = INFINITY, stride = 2h (<= 0),
- * tile_edge = 8, max_restarts = 0, flags = 0, time_limit_s = 0 (300 s). */
+ * tile_edge = 8, max_restarts = 0, flags = 0, time_limit_s = 0 (300 s),
+ * stride_h = 0 (unused). */
 void fmm_default_opts(fmm_opts *opts);
 
 /* Bytes of device workspace fmm_solve() needs for this problem (0 if the
@@ -152,6 +157,70 @@ int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream);
  * a[3i+1], a[3i+2], r[i]) for i < n, where a holds per-axis upwind values
  * (+INFINITY for an axis without one) and r = h / F.  All device pointers. */
 int fmm_eval_godunov(const double *a, const double *r, double *out, int64_t n, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent problems in one persistent launch.
+ *
+ * The problems may differ in grid size, spacing, speeds and seeds; they share
+ * the speed storage type and the options.  Their tiles are numbered
+ * consecutively and march from one shared work list, while every problem
+ * runs its own restart loop (Alg. 16): its own band minimum, bound and exit
+ * test, so a finished problem drops out and a slow one does not hold back
+ * the others' bounds.  The launch sequence contains kernels only (no host
+ * copies or memsets), so it can be captured into a HIP graph and replayed;
+ * a replay reads the problems' current F and seed arrays from the same
+ * addresses.
+ * ------------------------------------------------------------------------ */
+
+/* One problem of a batch.  The struct itself lives in host memory; the
+ * pointers it holds are device pointers with the meaning and layout of the
+ * fmm_solve() arguments of the same names. */
+typedef struct {
+    int64_t n0, n1, n2;
+    double h;
+    const void *F;
+    const int64_t *seed_idx;
+    const double *seed_val;
+    int64_t n_seeds;
+    double *T_out;
+    uint8_t *status_out; /* may be NULL */
+} fmm_problem;
+
+/* Bytes of device workspace for the batch (0 if invalid).  Only the sizes in
+ * `problems` are read.  At most 2^20 problems and 2^32 - 16 tiles in all. */
+size_t fmm_batch_workspace_bytes(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_dtype,
+                                 const fmm_opts *opts);
+
+/* Solve every problem of the batch (asynchronous on `stream`).  Each
+ * problem's outputs follow the fmm_solve() conventions and are identical to
+ * what fmm_solve() returns for that problem alone with the same options (up
+ * to rounding-order differences that the per-point solver cannot see: the
+ * accepted set and every value agree with a single solve to the tolerance
+ * the parity tests state).  Returns FMM_EINVAL for an invalid problem or
+ * option, FMM_ENOMEM for a small workspace. */
+int fmm_solve_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_dtype, const fmm_opts *opts,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* Synchronise `stream` and copy per-problem statistics of the last batch
+ * solved in `workspace` into out[0 .. n_problems) (host).  n_accepted,
+ * n_restarts (restarts of that problem's own loop) and max_abs_T are per
+ * problem; the counters of tile work, device_error, tile_edge,
+ * n_workgroups and the stage timings are those of the whole batch.  Return
+ * codes as fmm_get_stats(). */
+int fmm_get_batch_stats(const void *workspace, int64_t n_problems, fmm_stats *out, void *stream);
+
+/* Autotuner: solve the batch once untimed and `reps` times timed (HIP
+ * events on `stream`, minimum taken) for every pair of tile edge in
+ * edges[0 .. n_edges) and stride (in units of each problem's h) in
+ * strides_h[0 .. n_strides), then return in *best a copy of *opts (NULL:
+ * defaults) with the fastest tile_edge and stride_h.  ms_out (host, may be
+ * NULL) receives n_edges * n_strides times, edge-major, -1 for a pair whose
+ * solve failed.  The workspace must hold the largest candidate
+ * (fmm_batch_workspace_bytes() for each edge).  Synchronises `stream`; the
+ * problems' outputs hold the last candidate's solution afterwards. */
+int fmm_tune_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_dtype, const fmm_opts *opts,
+                   const int32_t *edges, int32_t n_edges, const double *strides_h, int32_t n_strides, int32_t reps,
+                   void *workspace, size_t workspace_bytes, void *stream, fmm_opts *best, float *ms_out);
 
 /* Human-readable text for a return code. */
 const char *fmm_strerror(int status);

@@ -6,6 +6,7 @@
 
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/fmm.h"
 #include "fmm_internal.h"
@@ -24,39 +25,61 @@ bool opts_ok(const fmm_opts *o)
 {
     if (!o) return true;
     if (isnan(o->band_width) || o->band_width < 0.0) return false;
-    if (isnan(o->stride) || isnan(o->inner_stride)) return false;
+    if (isnan(o->stride) || isnan(o->inner_stride) || isnan(o->stride_h)) return false;
     if (!(o->tile_edge == 0 || o->tile_edge == 4 || o->tile_edge == 8 || o->tile_edge == 16)) return false;
     if (o->max_restarts < 0) return false;
     if (o->flags & ~(uint32_t)(FMM_VALIDATE | FMM_TIMING | FMM_ONE_MARCH)) return false;
     return true;
 }
 
-Params make_params(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, double *T, const Layout &L,
-                   void *ws, double width, double stride, double inner, int64_t max_restarts,
-                   uint32_t time_limit_s)
+bool problem_ok(const fmm_problem &q)
+{
+    int32_t t[3];
+    uint64_t nt;
+    if (!tile_grid(q.n0, q.n1, q.n2, 4, t, &nt)) return false;
+    if (!(q.h > 0.0) || !isfinite(q.h)) return false;
+    if (!q.F || !q.T_out) return false;
+    if (q.n_seeds < 0 || (q.n_seeds > 0 && (!q.seed_idx || !q.seed_val))) return false;
+    return true;
+}
+
+std::vector<int64_t> dims_of(int64_t n, const fmm_problem *q)
+{
+    std::vector<int64_t> d((size_t)n * 3);
+    for (int64_t i = 0; i < n; i++) {
+        d[3 * i] = q[i].n0;
+        d[3 * i + 1] = q[i].n1;
+        d[3 * i + 2] = q[i].n2;
+    }
+    return d;
+}
+
+// Restart stride of one problem (Alg. 16's delta-s, world units).
+double stride_of(const fmm_opts &o, double h)
+{
+    if (o.stride_h > 0.0) return o.stride_h * h;
+    if (o.stride > 0.0) return o.stride;
+    return 2.0 * h;
+}
+
+Params make_params(const Layout &L, void *ws, const fmm_opts &o)
 {
     char *b = (char *)ws;
     Params P;
     memset(&P, 0, sizeof P);
-    P.n0 = n0;
-    P.n1 = n1;
-    P.n2 = n2;
-    P.t0 = L.t0;
-    P.t1 = L.t1;
-    P.t2 = L.t2;
+    P.n_inst = L.n_inst;
     P.ntiles = L.ntiles;
     P.mask_words = L.mask_words;
-    P.h = h;
-    P.width = width;
-    P.stride = stride;
-    P.inner = inner;
-    P.two_march = 1;
-    P.max_restarts = max_restarts;
+    P.width = o.band_width;
+    P.inner = (o.inner_stride > 0.0) ? o.inner_stride : INFINITY;
+    P.two_march = (o.flags & FMM_ONE_MARCH) ? 0 : 1;
+    P.max_restarts = o.max_restarts > 0 ? (int64_t)o.max_restarts : 0;
     // the driver reads the 100 MHz constant clock
-    P.time_limit_ticks = 100000000ull * (unsigned long long)(time_limit_s ? time_limit_s : 300u);
-    P.T = T;
-    P.F = F;
+    P.time_limit_ticks = 100000000ull * (unsigned long long)(o.time_limit_s ? o.time_limit_s : 300u);
     P.ctrl = (Ctrl *)(b + L.off_ctrl);
+    P.inst = (const Inst *)(b + L.off_inst);
+    P.ictl = (InstCtl *)(b + L.off_ictl);
+    P.tinst = (uint32_t *)(b + L.off_tinst);
     P.meta = (TileMeta *)(b + L.off_meta);
     P.dirty0 = (uint32_t *)(b + L.off_dirty0);
     P.dirty1 = (uint32_t *)(b + L.off_dirty1);
@@ -94,6 +117,133 @@ StageEvents *events_for(const void *ws, bool create)
     return &(g_events[ws] = e);
 }
 
+int run_batch(int64_t n, const fmm_problem *q, fmm_dtype F_dtype, const fmm_opts *opts, void *workspace,
+              size_t workspace_bytes, void *stream)
+{
+    if (n <= 0 || n > MAX_PROBLEMS || !q || !workspace) return FMM_EINVAL;
+    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return FMM_EINVAL;
+    if (!opts_ok(opts)) return FMM_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return FMM_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!problem_ok(q[i])) return FMM_EINVAL;
+    fmm_opts o;
+    if (opts)
+        o = *opts;
+    else
+        fmm_default_opts(&o);
+    const int E = resolve_edge(&o);
+    Layout L;
+    std::vector<uint32_t> bases((size_t)n);
+    const std::vector<int64_t> dims = dims_of(n, q);
+    if (!make_layout(n, dims.data(), E, F_dtype == FMM_F64 ? 8 : 4, &L, bases.data())) return FMM_EINVAL;
+    if (workspace_bytes < L.total) return FMM_ENOMEM;
+    Params P = make_params(L, workspace, o);
+    std::vector<Inst> insts((size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        Inst &I = insts[(size_t)i];
+        memset(&I, 0, sizeof I);
+        int32_t t[3];
+        uint64_t nt = 0;
+        tile_grid(q[i].n0, q[i].n1, q[i].n2, E, t, &nt);
+        I.n0 = q[i].n0;
+        I.n1 = q[i].n1;
+        I.n2 = q[i].n2;
+        I.t0 = t[0];
+        I.t1 = t[1];
+        I.t2 = t[2];
+        I.base = bases[(size_t)i];
+        I.ntiles = (uint32_t)nt;
+        I.h = q[i].h;
+        I.stride = stride_of(o, q[i].h);
+        I.F = q[i].F;
+        I.T = q[i].T_out;
+        I.status = q[i].status_out;
+        I.seed_idx = q[i].n_seeds > 0 ? q[i].seed_idx : nullptr;
+        I.seed_val = q[i].n_seeds > 0 ? q[i].seed_val : nullptr;
+        I.n_seeds = q[i].n_seeds;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = F_dtype == FMM_F64;
+    StageEvents *ev = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return FMM_EHIP;
+    // stage timing is a property of eager solves; a captured sequence has none
+    if (cs == hipStreamCaptureStatusActive) o.flags &= ~(uint32_t)FMM_TIMING;
+    if (o.flags & FMM_TIMING) {
+        ev = events_for(workspace, true);
+        if (!ev) return FMM_EHIP;
+        ev->valid = false;
+    } else if ((ev = events_for(workspace, false)) != nullptr) {
+        ev->valid = false;
+        ev = nullptr;
+    }
+    if (ev && hipEventRecord(ev->ev[0], s) != hipSuccess) return FMM_EHIP;
+    if (launch_prepare(P, insts.data(), n, E, (o.flags & FMM_VALIDATE) != 0, f64, s) != hipSuccess)
+        return FMM_EHIP;
+    if (ev && hipEventRecord(ev->ev[1], s) != hipSuccess) return FMM_EHIP;
+    uint32_t nwg = 0;
+    if (launch_driver(P, E, f64, s, &nwg) != hipSuccess) return FMM_EHIP;
+    if (ev && hipEventRecord(ev->ev[2], s) != hipSuccess) return FMM_EHIP;
+    if (launch_finalize(P, insts.data(), n, E, s) != hipSuccess) return FMM_EHIP;
+    if (ev) {
+        if (hipEventRecord(ev->ev[3], s) != hipSuccess) return FMM_EHIP;
+        ev->valid = true;
+    }
+    return FMM_OK;
+}
+
+// Statistics of problems [0, n) of the last solve in `workspace`.
+int read_stats(const void *workspace, int64_t n, fmm_stats *out, void *stream)
+{
+    if (!workspace || !out || n <= 0 || n > MAX_PROBLEMS) return FMM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Ctrl c;
+    if (hipMemcpyAsync(&c, workspace, sizeof c, hipMemcpyDeviceToHost, s) != hipSuccess) return FMM_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FMM_EHIP;
+    if (c.n_inst == 0 || (int64_t)c.n_inst < n) return FMM_EINVAL;
+    // the per-problem records follow the control block and the problem table
+    const size_t off_ictl = align_up(align_up(sizeof(Ctrl), 256) + sizeof(Inst) * (size_t)c.n_inst, 256);
+    std::vector<InstCtl> ic((size_t)n);
+    if (hipMemcpyAsync(ic.data(), (const char *)workspace + off_ictl, sizeof(InstCtl) * (size_t)n,
+                       hipMemcpyDeviceToHost, s) != hipSuccess)
+        return FMM_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FMM_EHIP;
+    double t[3] = {-1.0, -1.0, -1.0};
+    if (StageEvents *ev = events_for(workspace, false)) {
+        float x[3];
+        if (ev->valid && hipEventElapsedTime(&x[0], ev->ev[0], ev->ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&x[1], ev->ev[1], ev->ev[2]) == hipSuccess &&
+            hipEventElapsedTime(&x[2], ev->ev[2], ev->ev[3]) == hipSuccess) {
+            t[0] = x[0];
+            t[1] = x[1];
+            t[2] = x[2];
+        }
+    }
+    for (int64_t i = 0; i < n; i++) {
+        fmm_stats &o = out[i];
+        memset(&o, 0, sizeof o);
+        o.n_accepted = (int64_t)ic[(size_t)i].n_accepted;
+        o.n_restarts = (int64_t)ic[(size_t)i].restarts;
+        double m;
+        memcpy(&m, &ic[(size_t)i].max_abs_bits, sizeof m);
+        o.max_abs_T = m;
+        o.n_reopened = (int64_t)c.n_reopen;
+        o.n_tile_marches = (int64_t)c.n_march;
+        o.n_solves = (int64_t)c.n_solve;
+        o.n_rounds = (int64_t)c.n_round;
+        o.device_error = c.error | c.error_run;
+        o.tile_edge = c.tile_edge;
+        o.n_workgroups = (int64_t)c.nwg;
+        o.ms_prepare = t[0];
+        o.ms_driver = t[1];
+        o.ms_finalize = t[2];
+    }
+    const uint32_t err = c.error | c.error_run;
+    if (err & ERR_NOCONV) return FMM_ENOCONV;
+    if (err) return FMM_EDEVICE;
+    return FMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -108,6 +258,7 @@ void fmm_default_opts(fmm_opts *o)
     o->tile_edge = 8;
     o->max_restarts = 0;
     o->flags = 0;
+    o->stride_h = 0.0;
 }
 
 size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, fmm_dtype F_dtype,
@@ -116,7 +267,8 @@ size_t fmm_workspace_bytes(int64_t n0, int64_t n1, int64_t n2, int64_t n_seeds, 
     if (n_seeds < 0 || !opts_ok(opts)) return 0;
     if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return 0;
     Layout L;
-    if (!make_layout(n0, n1, n2, resolve_edge(opts), F_dtype == FMM_F64 ? 8 : 4, &L)) return 0;
+    const int64_t d[3] = {n0, n1, n2};
+    if (!make_layout(1, d, resolve_edge(opts), F_dtype == FMM_F64 ? 8 : 4, &L, nullptr)) return 0;
     return L.total;
 }
 
@@ -124,87 +276,115 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
               const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, const fmm_opts *opts,
               double *T_out, uint8_t *status_out, void *workspace, size_t workspace_bytes, void *stream)
 {
-    if (n0 <= 0 || n1 <= 0 || n2 <= 0) return FMM_EINVAL;
-    if (n0 > (1ll << 40) / n1 / n2) return FMM_EINVAL;
-    if (!(h > 0.0) || !isfinite(h)) return FMM_EINVAL;
-    if (!F || !T_out || !workspace) return FMM_EINVAL;
-    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return FMM_EINVAL;
-    if (n_seeds < 0 || (n_seeds > 0 && (!seed_idx || !seed_val))) return FMM_EINVAL;
-    if (!opts_ok(opts)) return FMM_EINVAL;
-    if (((uintptr_t)workspace & 255u) != 0) return FMM_EINVAL;
-    fmm_opts o;
-    if (opts)
-        o = *opts;
-    else
-        fmm_default_opts(&o);
-    const int E = resolve_edge(&o);
-    Layout L;
-    if (!make_layout(n0, n1, n2, E, F_dtype == FMM_F64 ? 8 : 4, &L)) return FMM_EINVAL;
-    if (workspace_bytes < L.total) return FMM_ENOMEM;
-    const double stride = (o.stride > 0.0) ? o.stride : 2.0 * h;
-    const int64_t maxr = o.max_restarts > 0 ? (int64_t)o.max_restarts : 0;
-    const double inner = (o.inner_stride > 0.0) ? o.inner_stride : INFINITY;
-    Params P = make_params(n0, n1, n2, h, F, T_out, L, workspace, o.band_width, stride, inner, maxr, o.time_limit_s);
-    P.two_march = (o.flags & FMM_ONE_MARCH) ? 0 : 1;
-    hipStream_t s = (hipStream_t)stream;
-    const bool f64 = F_dtype == FMM_F64;
-    StageEvents *ev = nullptr;
-    if (o.flags & FMM_TIMING) {
-        ev = events_for(workspace, true);
-        if (!ev) return FMM_EHIP;
-        ev->valid = false;
-    } else if ((ev = events_for(workspace, false)) != nullptr) {
-        ev->valid = false;
-        ev = nullptr;
-    }
-    if (ev && hipEventRecord(ev->ev[0], s) != hipSuccess) return FMM_EHIP;
-    if (launch_prepare(P, seed_idx, seed_val, n_seeds, E, (o.flags & FMM_VALIDATE) != 0, f64, s) != hipSuccess)
-        return FMM_EHIP;
-    if (ev && hipEventRecord(ev->ev[1], s) != hipSuccess) return FMM_EHIP;
-    uint32_t nwg = 0;
-    if (launch_driver(P, E, f64, s, &nwg) != hipSuccess) return FMM_EHIP;
-    if (ev && hipEventRecord(ev->ev[2], s) != hipSuccess) return FMM_EHIP;
-    if (launch_finalize(P, E, status_out, s) != hipSuccess) return FMM_EHIP;
-    if (ev) {
-        if (hipEventRecord(ev->ev[3], s) != hipSuccess) return FMM_EHIP;
-        ev->valid = true;
-    }
-    return FMM_OK;
+    fmm_problem q;
+    q.n0 = n0;
+    q.n1 = n1;
+    q.n2 = n2;
+    q.h = h;
+    q.F = F;
+    q.seed_idx = seed_idx;
+    q.seed_val = seed_val;
+    q.n_seeds = n_seeds;
+    q.T_out = T_out;
+    q.status_out = status_out;
+    return run_batch(1, &q, F_dtype, opts, workspace, workspace_bytes, stream);
 }
 
 int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream)
 {
-    if (!workspace || !out) return FMM_EINVAL;
+    return read_stats(workspace, 1, out, stream);
+}
+
+size_t fmm_batch_workspace_bytes(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_dtype,
+                                 const fmm_opts *opts)
+{
+    if (n_problems <= 0 || n_problems > MAX_PROBLEMS || !problems || !opts_ok(opts)) return 0;
+    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return 0;
+    Layout L;
+    const std::vector<int64_t> dims = dims_of(n_problems, problems);
+    if (!make_layout(n_problems, dims.data(), resolve_edge(opts), F_dtype == FMM_F64 ? 8 : 4, &L, nullptr))
+        return 0;
+    return L.total;
+}
+
+int fmm_solve_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_dtype, const fmm_opts *opts,
+                    void *workspace, size_t workspace_bytes, void *stream)
+{
+    return run_batch(n_problems, problems, F_dtype, opts, workspace, workspace_bytes, stream);
+}
+
+int fmm_get_batch_stats(const void *workspace, int64_t n_problems, fmm_stats *out, void *stream)
+{
+    return read_stats(workspace, n_problems, out, stream);
+}
+
+int fmm_tune_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_dtype, const fmm_opts *opts,
+                   const int32_t *edges, int32_t n_edges, const double *strides_h, int32_t n_strides, int32_t reps,
+                   void *workspace, size_t workspace_bytes, void *stream, fmm_opts *best, float *ms_out)
+{
+    if (!edges || n_edges <= 0 || !strides_h || n_strides <= 0 || reps <= 0 || !best) return FMM_EINVAL;
+    if (!opts_ok(opts)) return FMM_EINVAL;
+    fmm_opts base;
+    if (opts)
+        base = *opts;
+    else
+        fmm_default_opts(&base);
+    base.flags &= ~(uint32_t)FMM_TIMING;
+    for (int32_t a = 0; a < n_edges; a++) {
+        if (!(edges[a] == 4 || edges[a] == 8 || edges[a] == 16)) return FMM_EINVAL;
+        fmm_opts o = base;
+        o.tile_edge = edges[a];
+        const size_t need = fmm_batch_workspace_bytes(n_problems, problems, F_dtype, &o);
+        if (need == 0) return FMM_EINVAL;
+        if (need > workspace_bytes) return FMM_ENOMEM;
+    }
+    for (int32_t b = 0; b < n_strides; b++)
+        if (!(strides_h[b] > 0.0)) return FMM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    Ctrl c;
-    if (hipMemcpyAsync(&c, workspace, sizeof c, hipMemcpyDeviceToHost, s) != hipSuccess) return FMM_EHIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return FMM_EHIP;
-    memset(out, 0, sizeof *out);
-    out->n_accepted = (int64_t)c.n_accepted;
-    out->n_restarts = (int64_t)c.restarts;
-    out->n_reopened = (int64_t)c.n_reopen;
-    out->n_tile_marches = (int64_t)c.n_march;
-    out->n_solves = (int64_t)c.n_solve;
-    out->n_rounds = (int64_t)c.n_round;
-    double m;
-    memcpy(&m, &c.max_abs_bits, sizeof m);
-    out->max_abs_T = m;
-    out->device_error = c.error | c.error_run;
-    out->tile_edge = c.tile_edge;
-    out->n_workgroups = (int64_t)c.nwg;
-    out->ms_prepare = out->ms_driver = out->ms_finalize = -1.0;
-    if (StageEvents *ev = events_for(workspace, false)) {
-        float t[3];
-        if (ev->valid && hipEventElapsedTime(&t[0], ev->ev[0], ev->ev[1]) == hipSuccess &&
-            hipEventElapsedTime(&t[1], ev->ev[1], ev->ev[2]) == hipSuccess &&
-            hipEventElapsedTime(&t[2], ev->ev[2], ev->ev[3]) == hipSuccess) {
-            out->ms_prepare = t[0];
-            out->ms_driver = t[1];
-            out->ms_finalize = t[2];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return FMM_EHIP;
+    }
+    std::vector<fmm_stats> st((size_t)n_problems);
+    float best_ms = -1.0f;
+    int rc = FMM_OK;
+    for (int32_t a = 0; a < n_edges && rc == FMM_OK; a++) {
+        for (int32_t b = 0; b < n_strides && rc == FMM_OK; b++) {
+            fmm_opts o = base;
+            o.tile_edge = edges[a];
+            o.stride_h = strides_h[b];
+            float ms = -1.0f;
+            bool ok = true;
+            for (int32_t k = 0; k <= reps && ok; k++) {
+                if (k > 0 && hipEventRecord(e0, s) != hipSuccess) rc = FMM_EHIP;
+                int r = run_batch(n_problems, problems, F_dtype, &o, workspace, workspace_bytes, stream);
+                if (r != FMM_OK) {
+                    rc = r;
+                    break;
+                }
+                if (k > 0 && hipEventRecord(e1, s) != hipSuccess) rc = FMM_EHIP;
+                r = read_stats(workspace, n_problems, st.data(), stream);  // synchronises
+                if (r == FMM_EHIP) rc = r;
+                if (r != FMM_OK) ok = false;
+                float x = 0.0f;
+                if (k > 0 && ok && rc == FMM_OK) {
+                    if (hipEventElapsedTime(&x, e0, e1) != hipSuccess) rc = FMM_EHIP;
+                    if (ms < 0.0f || x < ms) ms = x;
+                }
+            }
+            if (!ok) ms = -1.0f;
+            if (ms_out) ms_out[a * n_strides + b] = ms;
+            if (ms >= 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                *best = o;
+            }
         }
     }
-    if (out->device_error & ERR_NOCONV) return FMM_ENOCONV;
-    if (out->device_error) return FMM_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FMM_OK) return rc;
+    if (best_ms < 0.0f) return FMM_EDEVICE;
     return FMM_OK;
 }
 

@@ -7,15 +7,46 @@
 
 namespace fmm {
 
-// Per-restart bookkeeping.  Restart r reads slot[r % 3] (band minimum per side,
-// live-tile list length, tiles left dirty by the previous restart) and
-// accumulates into slot[(r + 1) % 3]; slot[(r + 2) % 3] is cleared at its start.
+// Per-restart bookkeeping of the shared tile lists.  Restart r reads
+// slot[r % 3] (live-tile list length) and appends into slot[(r + 1) % 3];
+// slot[(r + 2) % 3] is cleared at its start.
 struct alignas(128) Slot {
+    uint32_t live_len;  // entries of the live-tile list for this restart
+    uint32_t d_len;     // tiles dirtied during march-1 of this restart
+    uint32_t pad[30];
+};
+
+// One problem of a batch: its grid, its place in the tile numbering and its
+// caller buffers.  A single solve is a batch of one.
+struct Inst {
+    int64_t n0, n1, n2;
+    int32_t t0, t1, t2;  // tiles per axis
+    uint32_t base;       // global index of the problem's first tile
+    uint32_t ntiles;
+    uint32_t pad;
+    double h, stride;
+    const void *F;  // row-major speeds
+    double *T;      // row-major output
+    uint8_t *status;
+    const int64_t *seed_idx;
+    const double *seed_val;
+    int64_t n_seeds;
+};
+
+// Per-problem restart state (Alg. 16 runs once per problem: its own minimum,
+// bound, dirty count and exit test).  Restart r reads slot[r % 3] and
+// accumulates into slot[(r + 1) % 3].
+struct alignas(64) InstSlot {
     unsigned long long gmin[2];  // bit patterns of non-negative doubles
-    uint32_t live_len;           // entries of the live-tile list for this restart
     uint32_t pending;            // tiles dirtied after the last march of the previous restart
-    uint32_t d_len;              // tiles dirtied during march-1 of this restart
-    uint32_t pad[25];
+    uint32_t pad[11];
+};
+struct alignas(128) InstCtl {
+    InstSlot slot[3];
+    uint32_t restarts;  // restart at which the exit test passed (0: still running)
+    uint32_t pad;
+    unsigned long long n_accepted;
+    unsigned long long max_abs_bits;
 };
 
 constexpr int WORK_SEGS = 8;  // item-list segments, one per XCD
@@ -25,16 +56,15 @@ struct Ctrl {
     alignas(128) uint32_t abort;
     uint32_t error;      // input errors found before the driver starts
     uint32_t error_run;  // errors raised while the restart driver runs
-    uint32_t restarts;
+    uint32_t restarts;   // restarts of the whole batch
     uint32_t nwg;
     uint32_t tile_edge;
+    uint32_t n_inst;  // problems of the last solve
     alignas(128) Slot slot[3];
     alignas(128) unsigned long long n_march;
     unsigned long long n_solve;
     unsigned long long n_round;
     unsigned long long n_reopen;
-    unsigned long long n_accepted;
-    unsigned long long max_abs_bits;
     // cycle counters of builds with FMM_PROFILE defined (zero otherwise)
     alignas(128) unsigned long long prof[16];
     // work counters of the phase loop: per phase (mod 3) one counter per
@@ -67,33 +97,63 @@ enum : uint32_t {
 // holds the tiled working copies of T and F (each tile's E^3 values
 // contiguous, axis 2 fastest inside the tile) and, per tile, the two faces
 // normal to axis 2 (the only halo faces that are strided in the tiled layout).
+// The tiles of the problems of a batch are numbered consecutively, problem by
+// problem; every per-tile array is indexed by that global number.
 struct Layout {
     int E;
-    int32_t t0, t1, t2;
-    uint32_t ntiles;
+    uint32_t n_inst;
+    uint32_t ntiles;      // over all problems
     uint32_t mask_words;  // 64-bit seed-mask words per tile
-    size_t off_ctrl, off_meta, off_dirty0, off_dirty1, off_epoch, off_flags, off_visit, off_text, off_mask,
-        off_list0, off_list1, off_dlist, off_Tt, off_Ft, off_Zf, total;
+    size_t off_ctrl, off_inst, off_ictl, off_tinst, off_meta, off_dirty0, off_dirty1, off_epoch, off_flags,
+        off_visit, off_text, off_mask, off_list0, off_list1, off_dlist, off_Tt, off_Ft, off_Zf, total;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-inline bool make_layout(int64_t n0, int64_t n1, int64_t n2, int E, size_t fsize, Layout *L)
+constexpr int64_t MAX_PROBLEMS = 1 << 20;
+
+// Tiles per axis of an n0 x n1 x n2 grid; false for an invalid grid.
+inline bool tile_grid(int64_t n0, int64_t n1, int64_t n2, int E, int32_t t[3], uint64_t *nt)
 {
     if (n0 <= 0 || n1 <= 0 || n2 <= 0) return false;
+    if (n0 > (1ll << 40) / n1 / n2) return false;
+    const int64_t a = (n0 + E - 1) / E, b = (n1 + E - 1) / E, c = (n2 + E - 1) / E;
+    if (a > INT32_MAX || b > INT32_MAX || c > INT32_MAX) return false;
+    t[0] = (int32_t)a;
+    t[1] = (int32_t)b;
+    t[2] = (int32_t)c;
+    *nt = (uint64_t)a * (uint64_t)b * (uint64_t)c;
+    return true;
+}
+
+// dims: 3 extents per problem.  bases (nullable): first global tile of each
+// problem.
+inline bool make_layout(int64_t n_inst, const int64_t *dims, int E, size_t fsize, Layout *L, uint32_t *bases)
+{
+    if (n_inst <= 0 || n_inst > MAX_PROBLEMS || !dims) return false;
     if (!(E == 4 || E == 8 || E == 16)) return false;
-    int64_t t0 = (n0 + E - 1) / E, t1 = (n1 + E - 1) / E, t2 = (n2 + E - 1) / E;
-    int64_t nt = t0 * t1 * t2;
-    if (nt >= (int64_t)0xFFFFFFF0u || t0 > INT32_MAX || t1 > INT32_MAX || t2 > INT32_MAX) return false;
+    uint64_t nt = 0;
+    for (int64_t i = 0; i < n_inst; i++) {
+        int32_t t[3];
+        uint64_t n = 0;
+        if (!tile_grid(dims[3 * i], dims[3 * i + 1], dims[3 * i + 2], E, t, &n)) return false;
+        if (bases) bases[i] = (uint32_t)nt;
+        nt += n;
+        if (nt >= 0xFFFFFFF0ull) return false;
+    }
     L->E = E;
-    L->t0 = (int32_t)t0;
-    L->t1 = (int32_t)t1;
-    L->t2 = (int32_t)t2;
+    L->n_inst = (uint32_t)n_inst;
     L->ntiles = (uint32_t)nt;
     L->mask_words = (uint32_t)((E * E * E + 63) / 64);
     size_t o = 0;
     L->off_ctrl = o;
     o = align_up(o + sizeof(Ctrl), 256);
+    L->off_inst = o;
+    o = align_up(o + sizeof(Inst) * (size_t)n_inst, 256);
+    L->off_ictl = o;
+    o = align_up(o + sizeof(InstCtl) * (size_t)n_inst, 256);
+    L->off_tinst = o;
+    o = align_up(o + 4 * nt, 256);
     L->off_meta = o;
     o = align_up(o + sizeof(TileMeta) * nt, 256);
     L->off_dirty0 = o;
@@ -128,16 +188,16 @@ inline bool make_layout(int64_t n0, int64_t n1, int64_t n2, int E, size_t fsize,
 }
 
 struct Params {
-    int64_t n0, n1, n2;
-    int32_t t0, t1, t2;
-    uint32_t ntiles;
+    uint32_t n_inst;
+    uint32_t ntiles;  // over all problems
     uint32_t mask_words;
-    double h, width, stride, inner;
+    double width, inner;
     int64_t max_restarts;
     int32_t two_march;  // second march of Alg. 16 after the exchange (1) or not (0)
     unsigned long long time_limit_ticks;  // restart-driver wall-clock limit (100 MHz ticks)
-    double *T;        // output, row-major (written by the finalize kernel)
-    const void *F;    // input speeds, row-major
+    const Inst *inst;     // problem descriptors
+    InstCtl *ictl;        // per-problem restart state and statistics
+    uint32_t *tinst;      // problem of each tile
     double *Tt;       // tiled working T
     void *Ft;         // tiled speeds (type of F)
     double *Zf;       // per tile: its i2 = 0 and i2 = E-1 faces
@@ -152,11 +212,12 @@ struct Params {
     uint32_t *list0, *list1, *dlist;
 };
 
-// Host-side launchers (defined in fmm_kernels.hip).
-hipError_t launch_prepare(const Params &P, const int64_t *seed_idx, const double *seed_val, int64_t n_seeds,
-                          int E, bool validate, bool f64, hipStream_t s);
+// Host-side launchers (defined in fmm_kernels.hip).  `insts` is a host array
+// of the n problem descriptors (the same values the workspace holds).
+hipError_t launch_prepare(const Params &P, const Inst *insts, int64_t n, int E, bool validate, bool f64,
+                          hipStream_t s);
 hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out);
-hipError_t launch_finalize(const Params &P, int E, uint8_t *status, hipStream_t s);
+hipError_t launch_finalize(const Params &P, const Inst *insts, int64_t n, int E, hipStream_t s);
 hipError_t launch_eval_godunov(const double *a, const double *r, double *out, int64_t n, hipStream_t s);
 
 }  // namespace fmm

@@ -24,6 +24,7 @@
 // order used by the specification of fmm_eval_godunov(); the file is compiled
 // with -ffp-contract=off so no multiply-add is fused.
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 
@@ -175,8 +176,10 @@ template <int E, typename FT> struct WaveLds {
     unsigned long long bm[12];            // per face and side: smallest changed band value
 };
 
+constexpr uint32_t NO_INST = 0xFFFFFFFFu;
+
 template <int NW> struct WgShared {
-    uint32_t cntL[NW], cntD[NW], pend[NW];
+    uint32_t cntL[NW], cntD[NW], pend[NW], inst[NW];
     double gmin0[NW], gmin1[NW];
     uint32_t baseL, baseD;
     uint32_t ok;
@@ -195,6 +198,7 @@ struct WaveState {
     unsigned long long prof[16];
 #endif
     uint32_t nL, nD;      // staged entries (wave-uniform)
+    uint32_t acc;         // problem the three accumulators below belong to (NO_INST: none)
     uint32_t pending;     // tiles newly dirtied for the next restart
     double gmin0, gmin1;  // running min of band minima
     unsigned long long n_march, n_round;  // wave-uniform counters
@@ -407,13 +411,13 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, doubl
 
 // Relaxation at level th until no candidate improves; returns the number of
 // rounds.  Candidates are taken 64 at a time: all evaluations of a chunk read
-// before any of its writes, later chunks see earlier ones (the list order is
-// fixed, so the result is deterministic, and the fixed point is the same).
+// before any of its writes, later chunks see earlier ones (the fixed point is
+// the same either way).
 // Neighbours are marked from the magnitudes the evaluation read; values only
 // decrease, so a neighbour lowered meanwhile is at worst marked needlessly,
 // never missed.
 template <int E, typename FT>
-__device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, const double th[2], const double lastb[2],
+__device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double h, const double th[2], const double lastb[2],
                                      WaveState &ws)
 {
     using G = Geo<E>;
@@ -434,7 +438,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, const d
             int p = 0;
             if (k < n) {
                 p = L.list[cur][k];
-                ch = eval_point(L, p, P.h, th, nv, vp, na, upd);
+                ch = eval_point(L, p, h, th, nv, vp, na, upd);
                 ws.n_solve++;
             }
             wave_sync();
@@ -537,6 +541,13 @@ __device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double
     wave_sync();
 }
 
+// What a tile march needs to know about the problem the tile belongs to.
+struct TileGeo {
+    uint32_t base;       // first tile of the problem
+    int32_t t0, t1, t2;  // tiles per axis of the problem
+    double h;
+};
+
 // ---------------------------------------------------------------------------
 // One activation of a tile by one wavefront: load tile + halo into LDS, relax
 // its band up to the restart bound (Alg. 12 via Alg. 10/11), write back the
@@ -548,7 +559,8 @@ __device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double
 // valid upper bound, and the writer's flag makes this tile read them again.
 
 template <int E, typename FT>
-__device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, uint32_t t, int mode, uint32_t dbits,
+__device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, const TileGeo &G0, uint32_t t, int mode,
+                                           uint32_t dbits,
                                            const double bnd[2], const double lastb[2], uint32_t epoch, uint32_t phase,
                                            bool second, WaveState &ws, uint32_t *listNext, uint32_t *cntNext,
                                            uint32_t *dlist, uint32_t *cntD, uint32_t *dprod)
@@ -559,10 +571,12 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
     const FT *__restrict__ Ft = (const FT *)P.Ft;
     double *__restrict__ Tt = P.Tt;
 
-    const int32_t tz = (int32_t)(t % (uint32_t)P.t2);
-    const int32_t ty = (int32_t)((t / (uint32_t)P.t2) % (uint32_t)P.t1);
-    const int32_t tx = (int32_t)(t / ((uint32_t)P.t2 * (uint32_t)P.t1));
-    const uint32_t tsx = (uint32_t)P.t1 * (uint32_t)P.t2, tsy = (uint32_t)P.t2;
+    // tile coordinates inside its problem; neighbours are t +- stride
+    const uint32_t tl = t - G0.base;
+    const int32_t tz = (int32_t)(tl % (uint32_t)G0.t2);
+    const int32_t ty = (int32_t)((tl / (uint32_t)G0.t2) % (uint32_t)G0.t1);
+    const int32_t tx = (int32_t)(tl / ((uint32_t)G0.t2 * (uint32_t)G0.t1));
+    const uint32_t tsx = (uint32_t)G0.t1 * (uint32_t)G0.t2, tsy = (uint32_t)G0.t2;
     const bool hasSeed = (P.tflags[t] & TF_SEED) != 0;
     const bool fresh = P.visit[t] == 0;  // never written: every cell is +inf
     const unsigned long long *mask = P.mask + (size_t)t * P.mask_words;
@@ -616,7 +630,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
                 int c0, c1, c2;
                 face_cell<E>(f, u, w, c0, c1, c2);
                 const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
-                const int32_t tna = ax == 0 ? P.t0 : ax == 1 ? P.t1 : P.t2;
+                const int32_t tna = ax == 0 ? G0.t0 : ax == 1 ? G0.t1 : G0.t2;
                 if (plus ? tca + 1 < tna : tca > 0) {
                     const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
                     const uint32_t tnb = plus ? t + ts : t - ts;
@@ -707,7 +721,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
     PROF_ADD(3, t_marked - t_loaded);
     for (;;) {
         PROF_CLOCK(t_r0);
-        rounds += relax(P, L, th, lastb, ws);
+        rounds += relax(P, L, G0.h, th, lastb, ws);
         PROF_CLOCK(t_r1);
         PROF_ADD(4, t_r1 - t_r0);
         PROF_ADD(8, 1);
@@ -786,7 +800,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
             const int f = lane, ax = f >> 1;
             const bool plus = f & 1;
             const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
-            const int32_t tna = ax == 0 ? P.t0 : ax == 1 ? P.t1 : P.t2;
+            const int32_t tna = ax == 0 ? G0.t0 : ax == 1 ? G0.t1 : G0.t2;
             if (plus ? tca + 1 < tna : tca > 0) {
                 const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
                 u = plus ? t + ts : t - ts;
@@ -841,10 +855,64 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, u
 // ---------------------------------------------------------------------------
 // Persistent restart driver (Alg. 16).
 
+// Alg. 16's exit test for one problem: no band value within the width on
+// either side (an empty band reports +inf) and no tile left dirty.
+__device__ __forceinline__ bool inst_done(double g0, double g1, uint32_t pend, double width)
+{
+    const bool done0 = !(g0 < FMM_INF && g0 <= width);
+    const bool done1 = !(g1 < FMM_INF && g1 <= width);
+    return done0 && done1 && pend == 0;
+}
+
+// The problem a wavefront is working on in the current restart: geometry,
+// band bound per side (Alg. 16: min(minval + stride, width)) and whether the
+// problem has already passed its exit test.
+struct InstView {
+    uint32_t j;
+    TileGeo g;
+    double bnd[2];
+    bool done;
+};
+
+__device__ __forceinline__ void load_inst(const Params &P, uint32_t j, uint32_t r, int mode, InstView &v)
+{
+    const Inst &I = P.inst[j];
+    v.j = j;
+    v.g.base = I.base;
+    v.g.t0 = I.t0;
+    v.g.t1 = I.t1;
+    v.g.t2 = I.t2;
+    v.g.h = I.h;
+    if (mode == MODE_INIT) {
+        // heap initialisation: only seeds are sources
+        v.bnd[0] = v.bnd[1] = -1.0;
+        v.done = false;
+        return;
+    }
+    InstSlot &S = P.ictl[j].slot[r % 3];
+    const double g0 = bitsd(ld_acq64(&S.gmin[0])), g1 = bitsd(ld_acq64(&S.gmin[1]));
+    v.done = inst_done(g0, g1, ld_acq(&S.pending), P.width);
+    v.bnd[0] = fmin(g0 + I.stride, P.width);
+    v.bnd[1] = fmin(g1 + I.stride, P.width);
+}
+
+// Hand a wavefront's band minima and dirty count to its problem's next slot.
+__device__ __forceinline__ void flush_acc(const Params &P, WaveState &ws, uint32_t r)
+{
+    if (ws.acc != NO_INST && (threadIdx.x & 63) == 0) {
+        InstSlot &S = P.ictl[ws.acc].slot[(r + 1) % 3];
+        if (ws.gmin0 < FMM_INF) atomicMin(&S.gmin[0], bits_of(ws.gmin0));
+        if (ws.gmin1 < FMM_INF) atomicMin(&S.gmin[1], bits_of(ws.gmin1));
+        if (ws.pending) atomicAdd(&S.pending, ws.pending);
+    }
+    ws.acc = NO_INST;
+    ws.pending = 0;
+    ws.gmin0 = ws.gmin1 = FMM_INF;
+}
+
 template <int E, int NW, typename FT>
 __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
-                                          uint32_t phase, const uint32_t *items, uint32_t nitems, const double bnd[2],
-                                          WaveState &ws)
+                                          uint32_t phase, const uint32_t *items, uint32_t nitems, WaveState &ws)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     Ctrl *c = P.ctrl;
@@ -872,6 +940,8 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
     uint32_t(*cnt)[32] = c->work[phase % 3];
     uint32_t seg = blockIdx.x % WORK_SEGS, left = WORK_SEGS;
     uint32_t claim = 0;
+    InstView iv;
+    iv.j = NO_INST;
     if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
     for (;;) {
         const uint32_t k = bcast0(claim);
@@ -886,7 +956,15 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
         if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
         if (ld_acq(&c->abort)) break;
         const uint32_t i = lo + k;
-        const uint32_t t = items[i];
+        const uint32_t t = __builtin_amdgcn_readfirstlane(items[i]);
+        const uint32_t j = P.n_inst == 1 ? 0u : __builtin_amdgcn_readfirstlane(P.tinst[t]);
+        if (j != iv.j) load_inst(P, j, r, mode, iv);
+        // a problem that passed its exit test takes no further part
+        if (iv.done) continue;
+        if (j != ws.acc) {
+            flush_acc(P, ws, r);
+            ws.acc = j;
+        }
         uint32_t dbits = 0;
         double lastb[2] = {-FMM_INF, -FMM_INF};
         if (mode != MODE_INIT) {
@@ -900,10 +978,11 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             unsigned long long *tx = P.text + (size_t)t * 6;
             unsigned long long xb[6];
 #pragma unroll
-            for (int k = 0; k < 6; k++) xb[k] = ld_acq64(&tx[k]);
+            for (int q = 0; q < 6; q++) xb[q] = ld_acq64(&tx[q]);
             const double p0 = fmin(m.tmin[0], fmin(bitsd(xb[0]), fmin(bitsd(xb[2]), bitsd(xb[4]))));
             const double p1 = fmin(m.tmin[1], fmin(bitsd(xb[1]), fmin(bitsd(xb[3]), bitsd(xb[5]))));
-            const bool due = dbits != 0 || (p0 < FMM_INF && p0 <= bnd[0]) || (p1 < FMM_INF && p1 <= bnd[1]);
+            const bool due =
+                dbits != 0 || (p0 < FMM_INF && p0 <= iv.bnd[0]) || (p1 < FMM_INF && p1 <= iv.bnd[1]);
             if (!due) {
                 // carried over unchanged to the next restart
                 ws.gmin0 = fmin(ws.gmin0, p0);
@@ -922,42 +1001,55 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             // current phase's slot stays for a later march
             if (lane == 0) {
 #pragma unroll
-                for (int k = 0; k < 6; k++)
-                    if ((uint32_t)(k >> 1) != phase % 3u && xb[k] != bits_of(FMM_INF))
-                        atomicExch(&tx[k], bits_of(FMM_INF));
+                for (int q = 0; q < 6; q++)
+                    if ((uint32_t)(q >> 1) != phase % 3u && xb[q] != bits_of(FMM_INF))
+                        atomicExch(&tx[q], bits_of(FMM_INF));
             }
             wave_sync();
         }
-        tile_march<E, FT>(P, L, t, mode, dbits, bnd, lastb, epoch, phase, second, ws, listNext, &nxt.live_len,
-                          P.dlist, &cur.d_len, dprod);
+        tile_march<E, FT>(P, L, iv.g, t, mode, dbits, iv.bnd, lastb, epoch, phase, second, ws, listNext,
+                          &nxt.live_len, P.dlist, &cur.d_len, dprod);
     }
 
     PROF_CLOCK(t_phase1);
     PROF_ADD(0, t_phase1 - t_phase0);
-    // ---- workgroup epilogue: one atomic per list / reduction per workgroup
+    // ---- workgroup epilogue: one atomic per list and per problem's
+    // reduction per workgroup
     if (lane == 0) {
         S.cntL[wid] = ws.nL;
         S.cntD[wid] = ws.nD;
         S.pend[wid] = ws.pending;
+        S.inst[wid] = ws.acc;
         S.gmin0[wid] = ws.gmin0;
         S.gmin1[wid] = ws.gmin1;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t tl = 0, td = 0, tp = 0;
-        double g0 = FMM_INF, g1 = FMM_INF;
+        uint32_t tl = 0, td = 0;
         for (int w = 0; w < NW; w++) {
             tl += S.cntL[w];
             td += S.cntD[w];
-            tp += S.pend[w];
-            g0 = fmin(g0, S.gmin0[w]);
-            g1 = fmin(g1, S.gmin1[w]);
         }
         S.baseL = tl ? atomicAdd(&nxt.live_len, tl) : 0u;
         S.baseD = td ? atomicAdd(&cur.d_len, td) : 0u;
-        if (tp) atomicAdd(&nxt.pending, tp);
-        if (g0 < FMM_INF) atomicMin(&nxt.gmin[0], bits_of(g0));
-        if (g1 < FMM_INF) atomicMin(&nxt.gmin[1], bits_of(g1));
+        // wavefronts holding the same problem are combined
+        for (int w = 0; w < NW; w++) {
+            const uint32_t j = S.inst[w];
+            if (j == NO_INST) continue;
+            uint32_t tp = 0;
+            double g0 = FMM_INF, g1 = FMM_INF;
+            for (int u = w; u < NW; u++) {
+                if (S.inst[u] != j) continue;
+                tp += S.pend[u];
+                g0 = fmin(g0, S.gmin0[u]);
+                g1 = fmin(g1, S.gmin1[u]);
+                if (u > w) S.inst[u] = NO_INST;
+            }
+            InstSlot &Z = P.ictl[j].slot[(r + 1) % 3];
+            if (tp) atomicAdd(&Z.pending, tp);
+            if (g0 < FMM_INF) atomicMin(&Z.gmin[0], bits_of(g0));
+            if (g1 < FMM_INF) atomicMin(&Z.gmin[1], bits_of(g1));
+        }
     }
     __syncthreads();
     uint32_t offL = S.baseL, offD = S.baseD;
@@ -965,9 +1057,10 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
         offL += S.cntL[w];
         offD += S.cntD[w];
     }
-    for (uint32_t k = lane; k < ws.nL; k += 64) listNext[offL + k] = L.stL[k];
-    for (uint32_t k = lane; k < ws.nD; k += 64) P.dlist[offD + k] = L.stD[k];
+    for (uint32_t q = lane; q < ws.nL; q += 64) listNext[offL + q] = L.stL[q];
+    for (uint32_t q = lane; q < ws.nD; q += 64) P.dlist[offD + q] = L.stD[q];
     ws.nL = ws.nD = 0;
+    ws.acc = NO_INST;
     ws.pending = 0;
     ws.gmin0 = ws.gmin1 = FMM_INF;
 }
@@ -984,6 +1077,7 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
     uint32_t gen = 0;
     WaveState ws;
     ws.nL = ws.nD = 0;
+    ws.acc = NO_INST;
     ws.pending = 0;
     ws.gmin0 = ws.gmin1 = FMM_INF;
     ws.n_march = ws.n_round = ws.n_solve = ws.n_reopen = 0;
@@ -995,18 +1089,19 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
     if (blockIdx.x == 0 && threadIdx.x == 0) c->nwg = nwg;
     // Phase sequence: heap initialisation (Alg. 9: only seeds are sources),
     // then per restart r = 1, 2, ...: march-1 over the live tiles, march-2
-    // over the tiles whose halo changed (Alg. 16).  One call site keeps the
-    // march inlined once.
+    // over the tiles whose halo changed (Alg. 16).  Every problem of a batch
+    // has its own bound and exit test; the phases are shared, and the batch
+    // ends when every problem has passed.  One call site keeps the march
+    // inlined once.
     int mode = MODE_INIT;
     uint32_t r = 0;
     uint32_t phase = 1;  // phases are numbered from 1; tile visit stamps refer to them
-    double bnd[2] = {-1.0, -1.0};
     const uint32_t *items = P.list0;
     uint32_t nitems = ld_acq(&c->slot[0].live_len);
     bool run = ld_acq(&c->error) == 0;
     while (run) {
         PROF_CLOCK(t_p0);
-        run_phase<E, NW, FT>(P, L, s_g, mode, r, phase, items, nitems, bnd, ws);
+        run_phase<E, NW, FT>(P, L, s_g, mode, r, phase, items, nitems, ws);
         PROF_CLOCK(t_p1);
         const bool passed = grid_barrier(c, gen, nwg, &s_g.ok);
         PROF_CLOCK(t_p2);
@@ -1021,27 +1116,40 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
             continue;
         }
         r++;
-        Slot &S = c->slot[r % 3];
-        const double g0 = bitsd(ld_acq64(&S.gmin[0])), g1 = bitsd(ld_acq64(&S.gmin[1]));
-        const uint32_t pend = ld_acq(&S.pending);
-        const uint32_t len = ld_acq(&S.live_len);
+        const uint32_t len = ld_acq(&c->slot[r % 3].live_len);
+        // Alg. 16 exit tests, one per problem, on the minima gathered in the
+        // restart that just ended.  Workgroup 0 also records when each problem
+        // finished and clears the slots of the restart after next.
+        int active = 0;
+        for (uint32_t k = threadIdx.x; k < P.n_inst; k += blockDim.x) {
+            InstCtl &ic = P.ictl[k];
+            InstSlot &S = ic.slot[r % 3];
+            const double g0 = bitsd(ld_acq64(&S.gmin[0])), g1 = bitsd(ld_acq64(&S.gmin[1]));
+            const bool done = inst_done(g0, g1, ld_acq(&S.pending), P.width);
+            active |= done ? 0 : 1;
+            if (blockIdx.x == 0) {
+                if (done && ic.restarts == 0) ic.restarts = r;
+                InstSlot &Z = ic.slot[(r + 2) % 3];
+                Z.gmin[0] = Z.gmin[1] = bits_of(FMM_INF);
+                Z.pending = 0;
+            }
+        }
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             Slot &Z = c->slot[(r + 2) % 3];
-            Z.gmin[0] = Z.gmin[1] = bits_of(FMM_INF);
-            Z.live_len = Z.pending = Z.d_len = 0;
+            Z.live_len = Z.d_len = 0;
         }
-        // Alg. 16 exit test: both sides have no band value within the width
-        // (an empty band reports +inf) and no tile is left dirty.
-        const bool done0 = !(g0 < FMM_INF && g0 <= P.width);
-        const bool done1 = !(g1 < FMM_INF && g1 <= P.width);
-        if (done0 && done1 && pend == 0) {
+        if (!__syncthreads_or(active)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) c->restarts = r;
             break;
         }
         if (P.max_restarts > 0 && (int64_t)r > P.max_restarts) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                atomicOr(&c->error_run, ERR_NOCONV);
-                c->restarts = r;
+            if (blockIdx.x == 0) {
+                for (uint32_t k = threadIdx.x; k < P.n_inst; k += blockDim.x)
+                    if (P.ictl[k].restarts == 0) P.ictl[k].restarts = r;
+                if (threadIdx.x == 0) {
+                    atomicOr(&c->error_run, ERR_NOCONV);
+                    c->restarts = r;
+                }
             }
             break;
         }
@@ -1062,9 +1170,6 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
                 break;
             }
         }
-        // bound = min(minval + stride, width) per side (Alg. 16)
-        bnd[0] = fmin(g0 + P.stride, P.width);
-        bnd[1] = fmin(g1 + P.stride, P.width);
         mode = MODE_M1;
         items = (r & 1) ? P.list1 : P.list0;
         nitems = len;
@@ -1085,9 +1190,25 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
 }
 
 // ---------------------------------------------------------------------------
-// Preparation (Alg. 8): workspace reset, tiled copy of F, seeds and the
-// initial tile list.  Tiles never written hold +inf implicitly (visit = 0), so
-// T is not filled.
+// Preparation (Alg. 8): problem table, workspace reset, tiled copy of F,
+// seeds and the initial tile list.  Tiles never written hold +inf implicitly
+// (visit = 0), so T is not filled.  Per-problem kernels take the problem's
+// descriptor by value.
+
+constexpr int INST_PACK = 16;
+struct InstPack {
+    Inst v[INST_PACK];
+    uint32_t first, n;
+};
+
+// Copy up to INST_PACK problem descriptors into the workspace table (kernel
+// arguments rather than a host copy, so the whole solve is a sequence of
+// kernel launches).
+__global__ void k_set_inst(Inst *dst, InstPack pk)
+{
+    const uint32_t k = threadIdx.x;
+    if (k < pk.n) dst[pk.first + k] = pk.v[k];
+}
 
 __global__ void k_init_ws(Params P, int E)
 {
@@ -1102,16 +1223,22 @@ __global__ void k_init_ws(Params P, int E)
         c->restarts = 0;
         c->nwg = 0;
         c->tile_edge = (uint32_t)E;
-        for (int k = 0; k < 3; k++) {
-            c->slot[k].gmin[0] = c->slot[k].gmin[1] = bits_of(FMM_INF);
-            c->slot[k].live_len = c->slot[k].pending = c->slot[k].d_len = 0;
-        }
+        c->n_inst = P.n_inst;
+        for (int k = 0; k < 3; k++) c->slot[k].live_len = c->slot[k].d_len = 0;
         c->n_march = c->n_solve = c->n_round = c->n_reopen = 0;
         for (int k = 0; k < 16; k++) c->prof[k] = 0;
         for (int k = 0; k < 3; k++)
             for (int g = 0; g < WORK_SEGS; g++) c->work[k][g][0] = 0;
-        c->n_accepted = 0;
-        c->max_abs_bits = 0;
+    }
+    for (int64_t i = i0; i < (int64_t)P.n_inst; i += stride) {
+        InstCtl &ic = P.ictl[i];
+        for (int k = 0; k < 3; k++) {
+            ic.slot[k].gmin[0] = ic.slot[k].gmin[1] = bits_of(FMM_INF);
+            ic.slot[k].pending = 0;
+        }
+        ic.restarts = 0;
+        ic.n_accepted = 0;
+        ic.max_abs_bits = 0;
     }
     for (int64_t i = i0; i < (int64_t)P.ntiles; i += stride) {
         TileMeta m;
@@ -1130,22 +1257,25 @@ __global__ void k_init_ws(Params P, int E)
     for (int64_t i = i0; i < nm; i += stride) P.mask[i] = 0ull;
 }
 
-// Tiled copy of the speeds: one workgroup per tile, 0 outside the grid.
-template <int E, typename FT> __global__ void k_tile_speed(Params P)
+// Tiled copy of one problem's speeds (0 outside its grid) and the problem
+// index of each of its tiles.  One workgroup per tile.
+template <int E, typename FT> __global__ void k_tile_speed(Params P, Inst I, uint32_t j)
 {
     constexpr int V = E * E * E;
-    const FT *F = (const FT *)P.F;
+    const FT *F = (const FT *)I.F;
     FT *Ft = (FT *)P.Ft;
-    const int64_t n12 = P.n1 * P.n2;
-    for (int64_t t = blockIdx.x; t < (int64_t)P.ntiles; t += gridDim.x) {
-        const int64_t tz = t % P.t2, ty = (t / P.t2) % P.t1, tx = t / ((int64_t)P.t2 * P.t1);
+    const int64_t n12 = I.n1 * I.n2;
+    for (int64_t tl = blockIdx.x; tl < (int64_t)I.ntiles; tl += gridDim.x) {
+        const int64_t tz = tl % I.t2, ty = (tl / I.t2) % I.t1, tx = tl / ((int64_t)I.t2 * I.t1);
+        const size_t t = (size_t)I.base + (size_t)tl;
         for (int p = threadIdx.x; p < V; p += blockDim.x) {
             const int i0 = p / (E * E), i1 = (p / E) % E, i2 = p % E;
             const int64_t g0 = tx * E + i0, g1 = ty * E + i1, g2 = tz * E + i2;
             FT f = (FT)0;
-            if (g0 < P.n0 && g1 < P.n1 && g2 < P.n2) f = F[g0 * n12 + g1 * P.n2 + g2];
-            Ft[(size_t)t * V + p] = f;
+            if (g0 < I.n0 && g1 < I.n1 && g2 < I.n2) f = F[g0 * n12 + g1 * I.n2 + g2];
+            Ft[t * V + p] = f;
         }
+        if (threadIdx.x == 0) P.tinst[t] = j;
     }
 }
 
@@ -1158,35 +1288,38 @@ __device__ __forceinline__ void add_init_tile(const Params &P, uint32_t t)
     }
 }
 
-// Locate a seed: tile index and interior index, or false if out of range.
-__device__ __forceinline__ bool seed_cell(const Params &P, int64_t g, int E, uint32_t &t, int &p, int l[3],
+// Locate a seed of problem I: global tile index and interior index, or false
+// if out of range.
+__device__ __forceinline__ bool seed_cell(const Inst &I, int64_t g, int E, uint32_t &t, int &p, int l[3],
                                           int64_t c[3])
 {
-    const int64_t N = P.n0 * P.n1 * P.n2;
+    const int64_t N = I.n0 * I.n1 * I.n2;
     if (g < 0 || g >= N) return false;
-    const int64_t i0 = g / (P.n1 * P.n2), rem = g - i0 * (P.n1 * P.n2);
-    const int64_t i1 = rem / P.n2, i2 = rem - i1 * P.n2;
+    const int64_t i0 = g / (I.n1 * I.n2), rem = g - i0 * (I.n1 * I.n2);
+    const int64_t i1 = rem / I.n2, i2 = rem - i1 * I.n2;
     c[0] = i0 / E;
     c[1] = i1 / E;
     c[2] = i2 / E;
     l[0] = (int)(i0 - c[0] * E);
     l[1] = (int)(i1 - c[1] * E);
     l[2] = (int)(i2 - c[2] * E);
-    t = (uint32_t)((c[0] * P.t1 + c[1]) * P.t2 + c[2]);
+    t = I.base + (uint32_t)((c[0] * I.t1 + c[1]) * I.t2 + c[2]);
     p = (l[0] * E + l[1]) * E + l[2];
     return true;
 }
 
 // Seeds, pass 1: validate, set the seed bits, and list the seed tiles and
 // the neighbours across any tile face a seed lies on.
-__global__ void k_seed_mark(Params P, const int64_t *__restrict__ idx, const double *__restrict__ val, int64_t ns,
-                            int E)
+__global__ void k_seed_mark(Params P, Inst I, int E)
 {
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t *__restrict__ idx = I.seed_idx;
+    const double *__restrict__ val = I.seed_val;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < I.n_seeds;
+         k += (int64_t)gridDim.x * blockDim.x) {
         uint32_t t;
         int p, l[3];
         int64_t c[3];
-        if (!seed_cell(P, idx[k], E, t, p, l, c)) {
+        if (!seed_cell(I, idx[k], E, t, p, l, c)) {
             atomicOr(&P.ctrl->error, ERR_SEED_RANGE);
             continue;
         }
@@ -1202,8 +1335,8 @@ __global__ void k_seed_mark(Params P, const int64_t *__restrict__ idx, const dou
         }
         atomicOr(&P.tflags[t], (uint32_t)TF_SEED);
         add_init_tile(P, t);
-        const uint32_t ts[3] = {(uint32_t)P.t1 * (uint32_t)P.t2, (uint32_t)P.t2, 1u};
-        const int32_t tn[3] = {P.t0, P.t1, P.t2};
+        const uint32_t ts[3] = {(uint32_t)I.t1 * (uint32_t)I.t2, (uint32_t)I.t2, 1u};
+        const int32_t tn[3] = {I.t0, I.t1, I.t2};
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
             if (l[ax] == 0 && c[ax] > 0) add_init_tile(P, t - ts[ax]);
@@ -1212,7 +1345,8 @@ __global__ void k_seed_mark(Params P, const int64_t *__restrict__ idx, const dou
     }
 }
 
-// Seeds, pass 2: every seed tile starts as +inf (tiled T and face buffer).
+// Seeds, pass 2 (all problems at once): every seed tile starts as +inf
+// (tiled T and face buffer).
 template <int E> __global__ void k_seed_fill(Params P)
 {
     constexpr int V = E * E * E, FACE = E * E;
@@ -1227,27 +1361,27 @@ template <int E> __global__ void k_seed_fill(Params P)
 }
 
 // Seeds, pass 3: the values (KNOWN_FIX points of Alg. 8).
-__global__ void k_seed_scatter(Params P, const int64_t *__restrict__ idx, const double *__restrict__ val, int64_t ns,
-                               int E)
+__global__ void k_seed_scatter(Params P, Inst I, int E)
 {
     if (P.ctrl->error) return;
     const int V = E * E * E, FACE = E * E;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ns; k += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < I.n_seeds;
+         k += (int64_t)gridDim.x * blockDim.x) {
         uint32_t t;
         int p, l[3];
         int64_t c[3];
-        if (!seed_cell(P, idx[k], E, t, p, l, c)) continue;
-        const double v = val[k];
+        if (!seed_cell(I, I.seed_idx[k], E, t, p, l, c)) continue;
+        const double v = I.seed_val[k];
         P.Tt[(size_t)t * V + p] = v;
         if (l[2] == 0) P.Zf[((size_t)t * 2 + 0) * FACE + l[0] * E + l[1]] = v;
         if (l[2] == E - 1) P.Zf[((size_t)t * 2 + 1) * FACE + l[0] * E + l[1]] = v;
     }
 }
 
-template <typename FT> __global__ void k_validate(Params P)
+template <typename FT> __global__ void k_validate(Params P, Inst I)
 {
-    const int64_t N = P.n0 * P.n1 * P.n2;
-    const FT *F = (const FT *)P.F;
+    const int64_t N = I.n0 * I.n1 * I.n2;
+    const FT *F = (const FT *)I.F;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
         bad |= !(fabs((double)F[i]) < FMM_INF);
@@ -1255,24 +1389,24 @@ template <typename FT> __global__ void k_validate(Params P)
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: row-major T (accepted points and seeds keep their values, all
-// others +inf), status bytes and statistics.  One workgroup handles a run of
-// E points along axis 2, i.e. one row of one tile, per thread group.
+// Finalize one problem: row-major T (accepted points and seeds keep their
+// values, all others +inf), status bytes and statistics.  Each thread
+// handles one grid point; a block covers a run of a grid row.
 
-template <int E> __global__ void k_finalize(Params P, uint8_t *__restrict__ status)
+template <int E> __global__ void k_finalize(Params P, Inst I, uint32_t j)
 {
     constexpr int V = E * E * E;
-    const int64_t rows = P.n0 * P.n1;
-    const int64_t chunks = (P.n2 + blockDim.x - 1) / blockDim.x;
+    const int64_t rows = I.n0 * I.n1;
+    const int64_t chunks = (I.n2 + blockDim.x - 1) / blockDim.x;
     unsigned long long acc = 0;
     double mx = 0.0;
     for (int64_t wi = blockIdx.x; wi < rows * chunks; wi += gridDim.x) {
         const int64_t row = wi / chunks, ch = wi - row * chunks;
         const int64_t i2 = ch * blockDim.x + threadIdx.x;
-        if (i2 >= P.n2) continue;
-        const int64_t i0 = row / P.n1, i1 = row - i0 * P.n1;
-        const int64_t g = row * P.n2 + i2;
-        const uint32_t t = (uint32_t)(((i0 / E) * P.t1 + i1 / E) * P.t2 + i2 / E);
+        if (i2 >= I.n2) continue;
+        const int64_t i0 = row / I.n1, i1 = row - i0 * I.n1;
+        const int64_t g = row * I.n2 + i2;
+        const uint32_t t = I.base + (uint32_t)(((i0 / E) * I.t1 + i1 / E) * I.t2 + i2 / E);
         const int p = (int)(((i0 % E) * E + i1 % E) * E + i2 % E);
         bool seed = false;
         if (P.tflags[t] & TF_SEED) seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
@@ -1295,8 +1429,8 @@ template <int E> __global__ void k_finalize(Params P, uint8_t *__restrict__ stat
         } else {
             st = 0;
         }
-        P.T[g] = out;
-        if (status) status[g] = st;
+        I.T[g] = out;
+        if (I.status) I.status[g] = st;
     }
     __shared__ unsigned long long s_acc[16];
     __shared__ double s_mx[16];
@@ -1315,8 +1449,8 @@ template <int E> __global__ void k_finalize(Params P, uint8_t *__restrict__ stat
             a += s_acc[w];
             m = fmax(m, s_mx[w]);
         }
-        if (a) atomicAdd(&P.ctrl->n_accepted, a);
-        atomicMax(&P.ctrl->max_abs_bits, bits_of(m));
+        if (a) atomicAdd(&P.ictl[j].n_accepted, a);
+        atomicMax(&P.ictl[j].max_abs_bits, bits_of(m));
     }
 }
 
@@ -1334,45 +1468,72 @@ static int num_cus()
     return cus;
 }
 
-template <int E> static hipError_t launch_prepare_t(const Params &P, const int64_t *seed_idx, const double *seed_val,
-                                                   int64_t n_seeds, bool validate, bool f64, hipStream_t s)
+template <int E> static hipError_t launch_prepare_t(const Params &P, const Inst *insts, int64_t n, bool validate,
+                                                   bool f64, hipStream_t s)
 {
     const int cus = num_cus();
-    hipLaunchKernelGGL(k_init_ws, dim3(cus * 4), dim3(256), 0, s, P, E);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const unsigned tb = (unsigned)std::min<int64_t>((int64_t)P.ntiles, (int64_t)cus * 32);
-    if (f64)
-        hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(256), 0, s, P);
-    else
-        hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(256), 0, s, P);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (n_seeds > 0) {
-        const unsigned blocks = (unsigned)std::min<int64_t>((n_seeds + 255) / 256, (int64_t)cus * 16);
-        hipLaunchKernelGGL(k_seed_mark, dim3(blocks), dim3(256), 0, s, P, seed_idx, seed_val, n_seeds, E);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_seed_fill<E>, dim3(cus * 8), dim3(256), 0, s, P);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_seed_scatter, dim3(blocks), dim3(256), 0, s, P, seed_idx, seed_val, n_seeds, E);
+    hipError_t e;
+    for (int64_t first = 0; first < n; first += INST_PACK) {
+        InstPack pk;
+        memset(&pk, 0, sizeof pk);
+        pk.first = (uint32_t)first;
+        pk.n = (uint32_t)std::min<int64_t>(INST_PACK, n - first);
+        for (uint32_t k = 0; k < pk.n; k++) pk.v[k] = insts[first + k];
+        hipLaunchKernelGGL(k_set_inst, dim3(1), dim3(64), 0, s, (Inst *)P.inst, pk);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (validate) {
+    const int64_t init_items = std::max<int64_t>((int64_t)P.ntiles, (int64_t)P.n_inst);
+    const unsigned ib = (unsigned)std::max<int64_t>(1, std::min<int64_t>((init_items + 255) / 256, (int64_t)cus * 4));
+    hipLaunchKernelGGL(k_init_ws, dim3(ib), dim3(256), 0, s, P, E);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int64_t j = 0; j < n; j++) {
+        const Inst &I = insts[j];
+        const unsigned tb = (unsigned)std::min<int64_t>((int64_t)I.ntiles, (int64_t)cus * 32);
         if (f64)
-            hipLaunchKernelGGL(k_validate<double>, dim3(cus * 8), dim3(256), 0, s, P);
+            hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(256), 0, s, P, I, (uint32_t)j);
         else
-            hipLaunchKernelGGL(k_validate<float>, dim3(cus * 8), dim3(256), 0, s, P);
+            hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(256), 0, s, P, I, (uint32_t)j);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    bool any_seeds = false;
+    for (int64_t j = 0; j < n; j++) {
+        const Inst &I = insts[j];
+        if (I.n_seeds <= 0) continue;
+        any_seeds = true;
+        const unsigned blocks = (unsigned)std::min<int64_t>((I.n_seeds + 255) / 256, (int64_t)cus * 16);
+        hipLaunchKernelGGL(k_seed_mark, dim3(blocks), dim3(256), 0, s, P, I, E);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (any_seeds) {
+        hipLaunchKernelGGL(k_seed_fill<E>, dim3(cus * 8), dim3(256), 0, s, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int64_t j = 0; j < n; j++) {
+            const Inst &I = insts[j];
+            if (I.n_seeds <= 0) continue;
+            const unsigned blocks = (unsigned)std::min<int64_t>((I.n_seeds + 255) / 256, (int64_t)cus * 16);
+            hipLaunchKernelGGL(k_seed_scatter, dim3(blocks), dim3(256), 0, s, P, I, E);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    if (validate) {
+        for (int64_t j = 0; j < n; j++) {
+            if (f64)
+                hipLaunchKernelGGL(k_validate<double>, dim3(cus * 8), dim3(256), 0, s, P, insts[j]);
+            else
+                hipLaunchKernelGGL(k_validate<float>, dim3(cus * 8), dim3(256), 0, s, P, insts[j]);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
 
-hipError_t launch_prepare(const Params &P, const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, int E,
-                          bool validate, bool f64, hipStream_t s)
+hipError_t launch_prepare(const Params &P, const Inst *insts, int64_t n, int E, bool validate, bool f64,
+                          hipStream_t s)
 {
     switch (E) {
-    case 4: return launch_prepare_t<4>(P, seed_idx, seed_val, n_seeds, validate, f64, s);
-    case 8: return launch_prepare_t<8>(P, seed_idx, seed_val, n_seeds, validate, f64, s);
-    case 16: return launch_prepare_t<16>(P, seed_idx, seed_val, n_seeds, validate, f64, s);
+    case 4: return launch_prepare_t<4>(P, insts, n, validate, f64, s);
+    case 8: return launch_prepare_t<8>(P, insts, n, validate, f64, s);
+    case 16: return launch_prepare_t<16>(P, insts, n, validate, f64, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1392,6 +1553,17 @@ template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Pa
     Params Pc = P;
     void *args[] = {&Pc};
     if (nwg_out) *nwg_out = grid;
+    // Under stream capture (a HIP graph) the launch is an ordinary kernel
+    // node: the grid is sized to one full occupancy wave, every predecessor
+    // in the stream has finished, so all workgroups are resident together.
+    // Should they not be, the barrier's bounded wait aborts the solve.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    if (cs == hipStreamCaptureStatusActive) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, Pc);
+        return hipGetLastError();
+    }
     return hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(NW * 64), args, 0, s);
 }
 
@@ -1407,16 +1579,28 @@ hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32
     }
 }
 
-hipError_t launch_finalize(const Params &P, int E, uint8_t *status, hipStream_t s)
+template <int E> static hipError_t launch_finalize_t(const Params &P, const Inst *insts, int64_t n, hipStream_t s)
 {
     const int cus = num_cus();
+    for (int64_t j = 0; j < n; j++) {
+        const Inst &I = insts[j];
+        const int64_t rows = I.n0 * I.n1 * ((I.n2 + 255) / 256);
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, (int64_t)cus * 16));
+        hipLaunchKernelGGL(k_finalize<E>, dim3(blocks), dim3(256), 0, s, P, I, (uint32_t)j);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_finalize(const Params &P, const Inst *insts, int64_t n, int E, hipStream_t s)
+{
     switch (E) {
-    case 4: hipLaunchKernelGGL(k_finalize<4>, dim3(cus * 16), dim3(256), 0, s, P, status); break;
-    case 8: hipLaunchKernelGGL(k_finalize<8>, dim3(cus * 16), dim3(256), 0, s, P, status); break;
-    case 16: hipLaunchKernelGGL(k_finalize<16>, dim3(cus * 16), dim3(256), 0, s, P, status); break;
+    case 4: return launch_finalize_t<4>(P, insts, n, s);
+    case 8: return launch_finalize_t<8>(P, insts, n, s);
+    case 16: return launch_finalize_t<16>(P, insts, n, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_eval_godunov(const double *a, const double *r, double *out, int64_t n, hipStream_t s)

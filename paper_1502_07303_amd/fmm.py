@@ -32,7 +32,7 @@ ST_FAR, ST_BAND, ST_ACCEPTED, ST_SEED, ST_NEG = 0, 1, 2, 3, 0x80
 class FmmOpts(ctypes.Structure):
     _fields_ = [("band_width", ctypes.c_double), ("stride", ctypes.c_double),
                 ("inner_stride", ctypes.c_double), ("tile_edge", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("time_limit_s", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("time_limit_s", ctypes.c_uint32), ("stride_h", ctypes.c_double)]
 
 
 class FmmStats(ctypes.Structure):
@@ -46,6 +46,12 @@ class FmmStats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FmmProblem(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("h", ctypes.c_double),
+                ("F", ctypes.c_void_p), ("seed_idx", ctypes.c_void_p), ("seed_val", ctypes.c_void_p),
+                ("n_seeds", ctypes.c_int64), ("T_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p)]
 
 
 class FmmError(RuntimeError):
@@ -77,6 +83,17 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_get_stats.restype = ctypes.c_int
     lib.fmm_eval_godunov.argtypes = [P, P, P, i64, P]
     lib.fmm_eval_godunov.restype = ctypes.c_int
+    PP = ctypes.POINTER(FmmProblem)
+    lib.fmm_batch_workspace_bytes.argtypes = [i64, PP, ctypes.c_int, ctypes.POINTER(FmmOpts)]
+    lib.fmm_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.fmm_solve_batch.argtypes = [i64, PP, ctypes.c_int, ctypes.POINTER(FmmOpts), P, ctypes.c_size_t, P]
+    lib.fmm_solve_batch.restype = ctypes.c_int
+    lib.fmm_get_batch_stats.argtypes = [P, i64, ctypes.POINTER(FmmStats), P]
+    lib.fmm_get_batch_stats.restype = ctypes.c_int
+    lib.fmm_tune_batch.argtypes = [i64, PP, ctypes.c_int, ctypes.POINTER(FmmOpts), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, P,
+                                   ctypes.c_size_t, P, ctypes.POINTER(FmmOpts), ctypes.POINTER(ctypes.c_float)]
+    lib.fmm_tune_batch.restype = ctypes.c_int
     lib.fmm_strerror.argtypes = [ctypes.c_int]
     lib.fmm_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -88,7 +105,7 @@ def strerror(code: int) -> str:
 
 
 def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, validate=False,
-              time_limit_s=0, timing=False, inner_stride=None, one_march=False) -> FmmOpts:
+              time_limit_s=0, timing=False, inner_stride=None, one_march=False, stride_h=None) -> FmmOpts:
     o = FmmOpts()
     load_library().fmm_default_opts(ctypes.byref(o))
     o.band_width = float(band_width)
@@ -98,6 +115,7 @@ def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, val
     o.max_restarts = int(max_restarts)
     o.flags = (FMM_VALIDATE if validate else 0) | (FMM_TIMING if timing else 0) | (FMM_ONE_MARCH if one_march else 0)
     o.time_limit_s = int(time_limit_s)
+    o.stride_h = 0.0 if stride_h is None else float(stride_h)
     return o
 
 
@@ -202,3 +220,112 @@ def eval_godunov(a: torch.Tensor, r: torch.Tensor) -> torch.Tensor:
     if rc != FMM_OK:
         raise FmmError(rc, f"fmm_eval_godunov: {strerror(rc)}")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Batches
+
+
+def _dtype_code(dt):
+    if dt == torch.float32:
+        return FMM_F32
+    if dt == torch.float64:
+        return FMM_F64
+    raise FmmError(FMM_EINVAL, f"unsupported speed dtype {dt}")
+
+
+class BatchSolver:
+    """Many problems in one persistent launch.
+
+    ``problems`` is a list of dicts with keys F (contiguous CUDA tensor, one
+    dtype for the batch), h, seed_idx (int64), seed_val (float64); T and
+    status outputs are allocated here (``self.T[i]``, ``self.status[i]``).
+    The descriptors hold raw device addresses: the tensors must stay alive and
+    in place for the solver's lifetime (a solve reads their current values).
+    """
+
+    def __init__(self, problems, band_width=math.inf, stride=None, stride_h=None, tile_edge=0, max_restarts=0,
+                 validate=False, time_limit_s=0, timing=False, inner_stride=None, one_march=False,
+                 with_status=True, workspace_edges=None):
+        self.lib = load_library()
+        if not problems:
+            raise FmmError(FMM_EINVAL, "empty batch")
+        self.keep = []
+        dt = problems[0]["F"].dtype
+        self.dtype = _dtype_code(dt)
+        dev = problems[0]["F"].device
+        n = len(problems)
+        arr = (FmmProblem * n)()
+        self.T, self.status = [], []
+        for i, q in enumerate(problems):
+            F, idx, val = q["F"], q["seed_idx"], q["seed_val"]
+            if F.dtype != dt or not F.is_cuda or not F.is_contiguous() or F.dim() != 3:
+                raise FmmError(FMM_EINVAL, f"problem {i}: F must be a contiguous 3-D CUDA tensor of the batch dtype")
+            if idx.dtype != torch.int64 or val.dtype != torch.float64 or idx.numel() != val.numel():
+                raise FmmError(FMM_EINVAL, f"problem {i}: seed_idx int64 and seed_val float64 of equal length")
+            if not (idx.is_contiguous() and val.is_contiguous()):
+                raise FmmError(FMM_EINVAL, f"problem {i}: seed arrays must be contiguous")
+            T = torch.empty(F.shape, dtype=torch.float64, device=dev)
+            st = torch.empty(F.shape, dtype=torch.uint8, device=dev) if with_status else None
+            self.T.append(T)
+            self.status.append(st)
+            self.keep += [F, idx, val]
+            p = arr[i]
+            p.n0, p.n1, p.n2 = (int(x) for x in F.shape)
+            p.h = float(q["h"])
+            p.F = F.data_ptr()
+            p.n_seeds = idx.numel()
+            p.seed_idx = idx.data_ptr() if idx.numel() else None
+            p.seed_val = val.data_ptr() if idx.numel() else None
+            p.T_out = T.data_ptr()
+            p.status_out = st.data_ptr() if st is not None else None
+        self.n = n
+        self.problems = arr
+        self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s, timing,
+                              inner_stride, one_march, stride_h)
+        edges = workspace_edges or [self.opts.tile_edge or 8]
+        nbytes = 0
+        for e in edges:
+            o = make_opts(band_width, stride, e, max_restarts, validate, time_limit_s, timing, inner_stride,
+                          one_march, stride_h)
+            b = int(self.lib.fmm_batch_workspace_bytes(n, arr, self.dtype, ctypes.byref(o)))
+            if b == 0:
+                raise FmmError(FMM_EINVAL, "invalid batch or options")
+            nbytes = max(nbytes, b)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+        self.nbytes = nbytes
+
+    def solve(self, stream=None) -> None:
+        """Enqueue the batch solve on the current (or given) stream."""
+        rc = self.lib.fmm_solve_batch(self.n, self.problems, self.dtype, ctypes.byref(self.opts), _ptr(self.ws),
+                                      self.nbytes, _stream_handle(stream))
+        if rc != FMM_OK:
+            raise FmmError(rc, f"fmm_solve_batch: {strerror(rc)}")
+
+    def stats(self, stream=None, check=True):
+        """Synchronise and return the per-problem statistics."""
+        st = (FmmStats * self.n)()
+        rc = self.lib.fmm_get_batch_stats(_ptr(self.ws), self.n, st, _stream_handle(stream))
+        if check and rc != FMM_OK:
+            bits = [m for b, m in DERR.items() if st[0].device_error & b]
+            raise FmmError(rc, f"batch solve failed on the device: {strerror(rc)} ({', '.join(bits)})")
+        return list(st)
+
+    def tune(self, edges=(4, 8, 16), strides_h=(1.0, 2.0, 4.0, 8.0), reps=1, stream=None):
+        """Time every (tile edge, stride) pair with the library's autotuner and
+        adopt the fastest.  Returns {(edge, stride_h): ms}."""
+        ne, ns = len(edges), len(strides_h)
+        e_arr = (ctypes.c_int32 * ne)(*[int(e) for e in edges])
+        s_arr = (ctypes.c_double * ns)(*[float(x) for x in strides_h])
+        ms = (ctypes.c_float * (ne * ns))()
+        best = FmmOpts()
+        rc = self.lib.fmm_tune_batch(self.n, self.problems, self.dtype, ctypes.byref(self.opts), e_arr, ne, s_arr,
+                                     ns, int(reps), _ptr(self.ws), self.nbytes, _stream_handle(stream),
+                                     ctypes.byref(best), ms)
+        if rc != FMM_OK:
+            raise FmmError(rc, f"fmm_tune_batch: {strerror(rc)}")
+        best.flags = self.opts.flags
+        self.opts = best
+        return {(int(edges[a]), float(strides_h[b])): float(ms[a * ns + b]) for a in range(ne) for b in range(ns)}

@@ -166,3 +166,29 @@ def random_small(shape=(16, 16, 16), n_sources: int = 2, seed: int = 0, fmin: fl
                     torch.from_numpy(idx).to(device),
                     torch.zeros(len(idx), dtype=torch.float64, device=device), width,
                     {"seed": seed})
+
+
+def batch_problems(n_problems: int = 64, seed: int = 0, edge_range=(32, 192), corr_len: float = 0.1,
+                   dtype=torch.float64, device="cpu") -> list:
+    """A batch of independent full-domain point-source problems of uneven
+    size: cube edges drawn uniformly from ``edge_range`` (inclusive), each
+    with its own smooth speed field F = 2^tanh(g) in (0.5, 2) (g a seeded
+    Gaussian field, correlation length ``corr_len``) stored as ``dtype``, and
+    1-4 distinct point sources with T = 0 at uniformly drawn grid points."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_problems):
+        n = int(rng.integers(edge_range[0], edge_range[1] + 1))
+        ns = int(rng.integers(1, 5))
+        g = gaussian_field(n, seed * 100003 + i, corr_len, device=device)
+        F = torch.exp(math.log(2.0) * torch.tanh(g.to(torch.float64))).to(dtype).contiguous()
+        del g
+        pts = set()
+        while len(pts) < ns:
+            pts.add(tuple(int(v) for v in rng.integers(0, n, size=3)))
+        pts = sorted(pts)
+        idx = np.array([linear_index((n, n, n), *p) for p in pts], dtype=np.int64)
+        out.append(Workload(f"batch_{i}_{n}", F, 1.0 / (n - 1), torch.from_numpy(idx).to(device),
+                            torch.zeros(len(idx), dtype=torch.float64, device=device), math.inf,
+                            {"seed": seed, "index": i, "sources": pts}))
+    return out

@@ -30,7 +30,8 @@ def declared_functions():
 def test_exports_every_declared_symbol(fmm):
     names = declared_functions()
     assert {"fmm_solve", "fmm_workspace_bytes", "fmm_get_stats", "fmm_strerror", "fmm_default_opts",
-            "fmm_eval_godunov"} <= set(names)
+            "fmm_eval_godunov", "fmm_solve_batch", "fmm_batch_workspace_bytes", "fmm_get_batch_stats",
+            "fmm_tune_batch"} <= set(names)
     out = subprocess.run(["nm", "-D", "--defined-only", fmm.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     exported = set(re.findall(r"\bT (fmm_\w+)", out))
@@ -42,13 +43,15 @@ def test_exports_every_declared_symbol(fmm):
 def test_struct_layout_matches_header(fmm, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include "fmm.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(fmm_opts), sizeof(fmm_stats),'
-                   ' offsetof(fmm_stats, max_abs_T), offsetof(fmm_stats, n_workgroups));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(fmm_opts), sizeof(fmm_stats),'
+                   ' offsetof(fmm_stats, max_abs_T), offsetof(fmm_stats, n_workgroups), offsetof(fmm_opts, stride_h),'
+                   ' sizeof(fmm_problem), offsetof(fmm_problem, status_out));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(fmm.FmmOpts), ctypes.sizeof(fmm.FmmStats),
-                    fmm.FmmStats.max_abs_T.offset, fmm.FmmStats.n_workgroups.offset]
+                    fmm.FmmStats.max_abs_T.offset, fmm.FmmStats.n_workgroups.offset, fmm.FmmOpts.stride_h.offset,
+                    ctypes.sizeof(fmm.FmmProblem), fmm.FmmProblem.status_out.offset]
 
 
 def test_default_opts(fmm):
@@ -123,3 +126,62 @@ def test_strerror(fmm):
 def test_eval_godunov_rejects_null(fmm):
     assert fmm.load_library().fmm_eval_godunov(None, None, None, 5, None) == fmm.FMM_EINVAL
     assert fmm.load_library().fmm_eval_godunov(None, None, None, 0, None) == fmm.FMM_OK
+
+
+# --------------------------------------------------------------------------
+# batches (host side)
+
+def _problems(fmm, shapes, h=0.1, ns=1):
+    fake = 0x100000  # never dereferenced: host validation or sizing only
+    arr = (fmm.FmmProblem * len(shapes))()
+    for p, sh in zip(arr, shapes):
+        p.n0, p.n1, p.n2 = sh
+        p.h = h
+        p.F = p.seed_idx = p.seed_val = p.T_out = fake
+        p.n_seeds = ns
+    return arr
+
+
+def test_batch_workspace_bytes(fmm):
+    lib = fmm.load_library()
+    one = lib.fmm_batch_workspace_bytes(1, _problems(fmm, [(40, 33, 47)]), fmm.FMM_F64, None)
+    assert one == lib.fmm_workspace_bytes(40, 33, 47, 1, fmm.FMM_F64, None) > 0
+    a = lib.fmm_workspace_bytes(32, 32, 32, 1, fmm.FMM_F64, None)
+    b = lib.fmm_workspace_bytes(96, 64, 40, 1, fmm.FMM_F64, None)
+    both = lib.fmm_batch_workspace_bytes(2, _problems(fmm, [(32, 32, 32), (96, 64, 40)]), fmm.FMM_F64, None)
+    # the per-tile arrays add up; the control block is shared
+    assert max(a, b) < both <= a + b
+    assert lib.fmm_batch_workspace_bytes(0, _problems(fmm, [(8, 8, 8)]), fmm.FMM_F64, None) == 0
+    assert lib.fmm_batch_workspace_bytes(2, _problems(fmm, [(8, 8, 8), (0, 8, 8)]), fmm.FMM_F64, None) == 0
+    assert lib.fmm_batch_workspace_bytes(1, None, fmm.FMM_F64, None) == 0
+
+
+def test_batch_rejects_bad_problems(fmm):
+    lib = fmm.load_library()
+    ws = ctypes.c_void_p(0x100000)
+    good = _problems(fmm, [(8, 8, 8), (9, 10, 11)])
+    assert lib.fmm_solve_batch(2, good, fmm.FMM_F64, None, ws, 64, None) == fmm.FMM_ENOMEM
+    for field, val in [("h", 0.0), ("F", None), ("T_out", None), ("n_seeds", -1), ("seed_idx", None), ("n1", 0)]:
+        bad = _problems(fmm, [(8, 8, 8), (9, 10, 11)])
+        setattr(bad[1], field, val)
+        assert lib.fmm_solve_batch(2, bad, fmm.FMM_F64, None, ws, 1 << 30, None) == fmm.FMM_EINVAL, field
+    assert lib.fmm_solve_batch(0, good, fmm.FMM_F64, None, ws, 1 << 30, None) == fmm.FMM_EINVAL
+    o = fmm.make_opts(stride_h=math.nan)
+    assert lib.fmm_solve_batch(2, good, fmm.FMM_F64, ctypes.byref(o), ws, 1 << 30, None) == fmm.FMM_EINVAL
+
+
+def test_tune_rejects_bad_candidates(fmm):
+    lib = fmm.load_library()
+    ws = ctypes.c_void_p(0x100000)
+    good = _problems(fmm, [(16, 16, 16)])
+    best = fmm.FmmOpts()
+    strides = (ctypes.c_double * 2)(1.0, 2.0)
+    for edges, wsb in [([5], 1 << 30), ([4, 8], 64)]:
+        e = (ctypes.c_int32 * len(edges))(*edges)
+        rc = lib.fmm_tune_batch(1, good, fmm.FMM_F64, None, e, len(edges), strides, 2, 1, ws, wsb, None,
+                                ctypes.byref(best), None)
+        assert rc == (fmm.FMM_EINVAL if wsb > 64 else fmm.FMM_ENOMEM)
+    e = (ctypes.c_int32 * 1)(8)
+    bad_s = (ctypes.c_double * 1)(0.0)
+    assert lib.fmm_tune_batch(1, good, fmm.FMM_F64, None, e, 1, bad_s, 1, 1, ws, 1 << 30, None,
+                              ctypes.byref(best), None) == fmm.FMM_EINVAL

