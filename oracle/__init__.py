@@ -39,6 +39,8 @@ def _load():
     i64, dbl = ctypes.c_int64, ctypes.c_double
     lib.oracle_godunov.argtypes = [dbl, dbl, dbl, dbl]
     lib.oracle_godunov.restype = dbl
+    lib.oracle_godunov_k.argtypes = [dbl, dbl, dbl, dbl, ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_godunov_k.restype = dbl
     lib.oracle_godunov_batch.argtypes = [P, P, P, i64]
     lib.oracle_godunov_batch.restype = None
     lib.oracle_solve.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, i64, dbl, P, P, P, i64,
@@ -57,6 +59,13 @@ def _ptr(a):
 def godunov(a1, a2, a3, r):
     """Local solver G(a1, a2, a3, r) of Alg. 11 (per-axis upwind values, +inf if absent)."""
     return _load().oracle_godunov(float(a1), float(a2), float(a3), float(r))
+
+
+def godunov_k(a1, a2, a3, r):
+    """(G, k): the local solve and how many of the sorted upwind values its root uses."""
+    k = ctypes.c_int(0)
+    u = _load().oracle_godunov_k(float(a1), float(a2), float(a3), float(r), ctypes.byref(k))
+    return u, k.value
 
 
 def godunov_batch(a, r):

@@ -92,32 +92,44 @@ static inline int side_of(double v) { return v < 0.0 ? -1 : 1; }
  * identity (sum a)^2 - k sum a^2 = -sum_{i<j} (a_i - a_j)^2 so that no
  * O(T^2/h^2) terms cancel.  Every operation is written out in the order shown
  * (this file is compiled with -ffp-contract=off). */
-double oracle_godunov(double x, double y, double z, double r)
+/* The same local solve, also reporting in *k how many of the sorted upwind
+ * values the returned root uses (1, 2 or 3; 0 when there is none).  Those k
+ * smallest per-axis values are the point's upwind set in the linearisation
+ * of the discrete equation (used by the adjoint reference). */
+double oracle_godunov_k(double x, double y, double z, double r, int *k)
 {
     double a1 = x, a2 = y, a3 = z, t;
     if (a1 > a2) { t = a1; a1 = a2; a2 = t; }
     if (a2 > a3) { t = a2; a2 = a3; a3 = t; }
     if (a1 > a2) { t = a1; a1 = a2; a2 = t; }
+    *k = 0;
     if (!(a1 < INFINITY)) return INFINITY;
     double r2 = r * r;
     double best = a1 + r;
+    *k = 1;
     if (a2 < INFINITY) {
         double d12 = a2 - a1;
         double D2 = 2.0 * r2 - d12 * d12;
         if (D2 >= 0.0) {
             double u2 = ((a1 + a2) + sqrt(D2)) * 0.5;
-            if (u2 > a2 && u2 < best) best = u2;
+            if (u2 > a2 && u2 < best) { best = u2; *k = 2; }
         }
         if (a3 < INFINITY) {
             double d13 = a3 - a1, d23 = a3 - a2;
             double D3 = 3.0 * r2 - ((d12 * d12 + d13 * d13) + d23 * d23);
             if (D3 >= 0.0) {
                 double u3 = (((a1 + a2) + a3) + sqrt(D3)) / 3.0;
-                if (u3 > a3 && u3 < best) best = u3;
+                if (u3 > a3 && u3 < best) { best = u3; *k = 3; }
             }
         }
     }
     return best;
+}
+
+double oracle_godunov(double x, double y, double z, double r)
+{
+    int k;
+    return oracle_godunov_k(x, y, z, r, &k);
 }
 
 /* Batch form for tests: out[i] = G(a[3i], a[3i+1], a[3i+2], r[i]). */
