@@ -222,6 +222,69 @@ int fmm_tune_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_
                    const int32_t *edges, int32_t n_edges, const double *strides_h, int32_t n_strides, int32_t reps,
                    void *workspace, size_t workspace_bytes, void *stream, fmm_opts *best, float *ms_out);
 
+/* ------------------------------------------------------------------------
+ * Adjoint: the gradient of a loss L(T) with respect to the speeds.
+ *
+ * The paper solves the first-order Godunov system (Eqs. 2-3) and does not
+ * differentiate it; this is an extension built on that discretisation.  At
+ * the solution every accepted non-seed point p with F_p > 0 satisfies
+ * sum_{q in U_p} (|T_p| - |T_q|)^2 = (h / F_p)^2, where U_p holds, for each
+ * of the k axes whose values the local solver's root used (Alg. 11), the
+ * neighbour on that axis with the smaller |T| (the lower index on a tie).
+ * Seeds and points outside the accepted set are fixed.  The adjoint solves the
+ * transpose of the linearised system A d|T| = B dF exactly, in reverse
+ * dependency order (descending |T|), where row p of A has S_p on the diagonal
+ * (S_p = sum_{q in U_p} (|T_p| - |T_q|)) and -(|T_p| - |T_q|) at q in U_p, and
+ * B_p = -h^2 / F_p^3.  It returns dL/dF = B A^-T (sign(T) dL/dT), which is 0
+ * at seeds, at points outside the accepted set and where F <= 0.  U_p is recomputed from the forward
+ * solution, so nothing besides T and the status bytes needs to be kept.
+ * Where the solution map has a kink (two neighbours of an axis with equal
+ * values, or a change of k exactly at the solution) this is one of the
+ * one-sided derivatives.
+ * ------------------------------------------------------------------------ */
+
+/* One adjoint problem: the forward problem's grid, spacing and speeds, its
+ * solution (T_out and status_out of fmm_solve or fmm_solve_batch), the
+ * gradient of the loss with respect to T (entries outside the accepted set
+ * are ignored) and the output.  All pointers are device pointers, row-major
+ * (n0, n1, n2).  Several problems may share one dL_dF array: their gradients
+ * are summed (e.g. many sources over one speed model). */
+typedef struct {
+    int64_t n0, n1, n2;
+    double h;
+    const void *F;
+    const double *T;
+    const uint8_t *status;
+    const double *dL_dT;
+    double *dL_dF;
+} fmm_adjoint_problem;
+
+typedef struct {
+    int64_t n_points;      /* equations in the linear system (accepted non-seed points with F > 0) */
+    int64_t n_levels;      /* dependency levels processed (frontiers of the reverse sweep)          */
+    uint32_t device_error; /* FMM_DERR_BARRIER on a barrier timeout, else 0                          */
+    uint32_t pad;
+} fmm_adjoint_stats;
+
+/* Device workspace for an adjoint batch (0 if invalid): about 29 bytes per
+ * grid point of all problems. */
+size_t fmm_adjoint_workspace_bytes(int64_t n_problems, const fmm_adjoint_problem *problems);
+
+/* dL/dF of every problem of the batch (asynchronous on `stream`; each dL_dF
+ * is overwritten, or summed over the problems that share it).  Returns
+ * FMM_EINVAL for an invalid problem, FMM_ENOMEM for a small workspace. */
+int fmm_adjoint_batch(int64_t n_problems, const fmm_adjoint_problem *problems, fmm_dtype F_dtype,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Single-problem form of fmm_adjoint_batch(). */
+int fmm_adjoint(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_dtype F_dtype, const double *T,
+                const uint8_t *status, const double *dL_dT, double *dL_dF, void *workspace, size_t workspace_bytes,
+                void *stream);
+
+/* Synchronise `stream` and read the statistics of the last adjoint run in
+ * `workspace`; returns FMM_EDEVICE if the device recorded an error. */
+int fmm_get_adjoint_stats(const void *workspace, fmm_adjoint_stats *out, void *stream);
+
 /* Human-readable text for a return code. */
 const char *fmm_strerror(int status);
 

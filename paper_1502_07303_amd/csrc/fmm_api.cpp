@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/fmm.h"
+#include "fmm_adjoint.h"
 #include "fmm_internal.h"
 
 using namespace fmm;
@@ -386,6 +387,107 @@ int fmm_tune_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_
     if (rc != FMM_OK) return rc;
     if (best_ms < 0.0f) return FMM_EDEVICE;
     return FMM_OK;
+}
+
+static bool adj_problem_ok(const fmm_adjoint_problem &q)
+{
+    int32_t t[3];
+    uint64_t nt;
+    if (!tile_grid(q.n0, q.n1, q.n2, 4, t, &nt)) return false;
+    if (!(q.h > 0.0) || !isfinite(q.h)) return false;
+    return q.F && q.T && q.status && q.dL_dT && q.dL_dF;
+}
+
+static uint64_t adj_total(int64_t n, const fmm_adjoint_problem *q, std::vector<AdjInst> *insts)
+{
+    uint64_t total = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (insts) {
+            AdjInst &I = (*insts)[(size_t)i];
+            memset(&I, 0, sizeof I);
+            I.n0 = q[i].n0;
+            I.n1 = q[i].n1;
+            I.n2 = q[i].n2;
+            I.base = (int64_t)total;
+            I.h = q[i].h;
+            I.F = q[i].F;
+            I.T = q[i].T;
+            I.status = q[i].status;
+            I.dL_dT = q[i].dL_dT;
+            I.dL_dF = q[i].dL_dF;
+        }
+        total += (uint64_t)(q[i].n0 * q[i].n1 * q[i].n2);
+    }
+    return total;
+}
+
+size_t fmm_adjoint_workspace_bytes(int64_t n_problems, const fmm_adjoint_problem *problems)
+{
+    if (n_problems <= 0 || n_problems > MAX_PROBLEMS || !problems) return 0;
+    for (int64_t i = 0; i < n_problems; i++) {
+        int32_t t[3];
+        uint64_t nt;
+        if (!tile_grid(problems[i].n0, problems[i].n1, problems[i].n2, 4, t, &nt)) return 0;
+    }
+    return adj_layout(n_problems, adj_total(n_problems, problems, nullptr)).total;
+}
+
+int fmm_adjoint_batch(int64_t n_problems, const fmm_adjoint_problem *problems, fmm_dtype F_dtype,
+                      void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (n_problems <= 0 || n_problems > MAX_PROBLEMS || !problems || !workspace) return FMM_EINVAL;
+    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return FMM_EINVAL;
+    if (((uintptr_t)workspace & 255u) != 0) return FMM_EINVAL;
+    for (int64_t i = 0; i < n_problems; i++)
+        if (!adj_problem_ok(problems[i])) return FMM_EINVAL;
+    std::vector<AdjInst> insts((size_t)n_problems);
+    const uint64_t total = adj_total(n_problems, problems, &insts);
+    if (total >= (1ull << 40)) return FMM_EINVAL;
+    const AdjLayout L = adj_layout(n_problems, total);
+    if (workspace_bytes < L.total) return FMM_ENOMEM;
+    char *b = (char *)workspace;
+    AdjParams P;
+    P.ctrl = (AdjCtrl *)(b + L.off_ctrl);
+    P.inst = (const AdjInst *)(b + L.off_inst);
+    P.acc = (double *)(b + L.off_acc);
+    P.cnt = (uint32_t *)(b + L.off_cnt);
+    P.code = (uint8_t *)(b + L.off_code);
+    P.list0 = (uint64_t *)(b + L.off_list0);
+    P.list1 = (uint64_t *)(b + L.off_list1);
+    if (launch_adjoint(P, insts.data(), n_problems, F_dtype == FMM_F64, (hipStream_t)stream) != hipSuccess)
+        return FMM_EHIP;
+    return FMM_OK;
+}
+
+int fmm_adjoint(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_dtype F_dtype, const double *T,
+                const uint8_t *status, const double *dL_dT, double *dL_dF, void *workspace, size_t workspace_bytes,
+                void *stream)
+{
+    fmm_adjoint_problem q;
+    q.n0 = n0;
+    q.n1 = n1;
+    q.n2 = n2;
+    q.h = h;
+    q.F = F;
+    q.T = T;
+    q.status = status;
+    q.dL_dT = dL_dT;
+    q.dL_dF = dL_dF;
+    return fmm_adjoint_batch(1, &q, F_dtype, workspace, workspace_bytes, stream);
+}
+
+int fmm_get_adjoint_stats(const void *workspace, fmm_adjoint_stats *out, void *stream)
+{
+    if (!workspace || !out) return FMM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    AdjCtrl c;
+    if (hipMemcpyAsync(&c, workspace, sizeof c, hipMemcpyDeviceToHost, s) != hipSuccess) return FMM_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return FMM_EHIP;
+    memset(out, 0, sizeof *out);
+    out->n_points = (int64_t)c.n_points;
+    out->n_levels = (int64_t)c.levels;
+    out->device_error = c.error;
+    return c.error ? FMM_EDEVICE : FMM_OK;
 }
 
 int fmm_eval_godunov(const double *a, const double *r, double *out, int64_t n, void *stream)

@@ -28,90 +28,16 @@
 
 #include <algorithm>
 
+#include "fmm_device.h"
 #include "fmm_internal.h"
 
 namespace fmm {
-
-#define FMM_INF __builtin_huge_val()
-
-// ---------------------------------------------------------------------------
-// Local solver (Alg. 11 with Eqs. 4-7).  a = per-axis upwind values (+inf when
-// an axis has no upwind neighbour), r = h / F.  With a1 <= a2 <= a3:
-//   u1 = a1 + r
-//   u2 = ((a1 + a2) + sqrt(2 r^2 - (a2 - a1)^2)) * 0.5          causal iff u2 > a2
-//   u3 = (((a1 + a2) + a3) + sqrt(3 r^2 - (((a2-a1)^2 + (a3-a1)^2) + (a3-a2)^2))) / 3
-//                                                                causal iff u3 > a3
-// and G is the smallest causal root (discriminants must be >= 0).  This is the
-// paper's quadratic with the identity (sum a)^2 - k sum a^2 = -sum_{i<j}(a_i-a_j)^2
-// applied, so nothing of size T^2/h^2 cancels.
-__device__ __forceinline__ double godunov(double x, double y, double z, double r)
-{
-    double lo = fmin(x, y), hi = fmax(x, y);
-    double a3 = fmax(hi, z), m = fmin(hi, z);
-    double a1 = fmin(lo, m), a2 = fmax(lo, m);
-    if (!(a1 < FMM_INF)) return FMM_INF;
-    double r2 = r * r;
-    double best = a1 + r;
-    if (a2 < FMM_INF) {
-        double d12 = a2 - a1;
-        double D2 = 2.0 * r2 - d12 * d12;
-        if (D2 >= 0.0) {
-            double u2 = ((a1 + a2) + sqrt(D2)) * 0.5;
-            if (u2 > a2 && u2 < best) best = u2;
-        }
-        if (a3 < FMM_INF) {
-            double d13 = a3 - a1, d23 = a3 - a2;
-            double D3 = 3.0 * r2 - ((d12 * d12 + d13 * d13) + d23 * d23);
-            if (D3 >= 0.0) {
-                double u3 = (((a1 + a2) + a3) + sqrt(D3)) / 3.0;
-                if (u3 > a3 && u3 < best) best = u3;
-            }
-        }
-    }
-    return best;
-}
 
 __global__ void k_eval_godunov(const double *__restrict__ a, const double *__restrict__ r,
                                double *__restrict__ out, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = godunov(a[3 * i], a[3 * i + 1], a[3 * i + 2], r[i]);
-}
-
-// ---------------------------------------------------------------------------
-// Small helpers.
-
-__device__ __forceinline__ unsigned long long bits_of(double x) { return (unsigned long long)__double_as_longlong(x); }
-__device__ __forceinline__ double bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <typename T> __device__ __forceinline__ T bcast0(T v) { return __shfl(v, 0); }
-
-__device__ __forceinline__ double wave_min(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t ld_acq(uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_acq64(unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,32 +138,7 @@ struct WaveState {
 
 __device__ bool grid_barrier(Ctrl *c, uint32_t &gen, uint32_t nwg, uint32_t *s_ok)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        gen++;
-        uint32_t target = gen * nwg;
-        uint32_t ok = 1;
-        __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long t0 = wall_clock64();
-        while (ld_acq(&c->bar) < target) {
-            if (ld_acq(&c->abort)) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-            if (wall_clock64() - t0 > 2000000000ull) {  // 20 s at the 100 MHz constant clock
-                atomicOr(&c->error_run, ERR_BARRIER);
-                atomicExch(&c->abort, 1u);
-                ok = 0;
-                break;
-            }
-        }
-        *s_ok = ok;
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    return *s_ok != 0;
+    return grid_sync(&c->bar, &c->abort, &c->error_run, ERR_BARRIER, gen, nwg, s_ok);
 }
 
 // ---------------------------------------------------------------------------

@@ -54,6 +54,17 @@ class FmmProblem(ctypes.Structure):
                 ("n_seeds", ctypes.c_int64), ("T_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p)]
 
 
+class FmmAdjointProblem(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("h", ctypes.c_double),
+                ("F", ctypes.c_void_p), ("T", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("dL_dT", ctypes.c_void_p), ("dL_dF", ctypes.c_void_p)]
+
+
+class FmmAdjointStats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_levels", ctypes.c_int64), ("device_error", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
 class FmmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(msg)
@@ -94,6 +105,15 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32, P,
                                    ctypes.c_size_t, P, ctypes.POINTER(FmmOpts), ctypes.POINTER(ctypes.c_float)]
     lib.fmm_tune_batch.restype = ctypes.c_int
+    PA = ctypes.POINTER(FmmAdjointProblem)
+    lib.fmm_adjoint_workspace_bytes.argtypes = [i64, PA]
+    lib.fmm_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    lib.fmm_adjoint_batch.argtypes = [i64, PA, ctypes.c_int, P, ctypes.c_size_t, P]
+    lib.fmm_adjoint_batch.restype = ctypes.c_int
+    lib.fmm_adjoint.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, P, P, P, ctypes.c_size_t, P]
+    lib.fmm_adjoint.restype = ctypes.c_int
+    lib.fmm_get_adjoint_stats.argtypes = [P, ctypes.POINTER(FmmAdjointStats), P]
+    lib.fmm_get_adjoint_stats.restype = ctypes.c_int
     lib.fmm_strerror.argtypes = [ctypes.c_int]
     lib.fmm_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -246,7 +266,7 @@ class BatchSolver:
 
     def __init__(self, problems, band_width=math.inf, stride=None, stride_h=None, tile_edge=0, max_restarts=0,
                  validate=False, time_limit_s=0, timing=False, inner_stride=None, one_march=False,
-                 with_status=True, workspace_edges=None):
+                 with_status=True, workspace_edges=None, T_out=None, status_out=None):
         self.lib = load_library()
         if not problems:
             raise FmmError(FMM_EINVAL, "empty batch")
@@ -265,8 +285,18 @@ class BatchSolver:
                 raise FmmError(FMM_EINVAL, f"problem {i}: seed_idx int64 and seed_val float64 of equal length")
             if not (idx.is_contiguous() and val.is_contiguous()):
                 raise FmmError(FMM_EINVAL, f"problem {i}: seed arrays must be contiguous")
-            T = torch.empty(F.shape, dtype=torch.float64, device=dev)
-            st = torch.empty(F.shape, dtype=torch.uint8, device=dev) if with_status else None
+            if T_out is not None:
+                T = T_out[i]
+                if T.dtype != torch.float64 or T.shape != F.shape or not T.is_contiguous():
+                    raise FmmError(FMM_EINVAL, f"problem {i}: T_out must be contiguous float64 of F's shape")
+            else:
+                T = torch.empty(F.shape, dtype=torch.float64, device=dev)
+            if status_out is not None:
+                st = status_out[i]
+                if st.dtype != torch.uint8 or st.shape != F.shape or not st.is_contiguous():
+                    raise FmmError(FMM_EINVAL, f"problem {i}: status_out must be contiguous uint8 of F's shape")
+            else:
+                st = torch.empty(F.shape, dtype=torch.uint8, device=dev) if with_status else None
             self.T.append(T)
             self.status.append(st)
             self.keep += [F, idx, val]
@@ -329,3 +359,129 @@ class BatchSolver:
         best.flags = self.opts.flags
         self.opts = best
         return {(int(edges[a]), float(strides_h[b])): float(ms[a * ns + b]) for a in range(ne) for b in range(ns)}
+
+
+# ---------------------------------------------------------------------------
+# Adjoint
+
+
+class AdjointSolver:
+    """Reusable adjoint context for a fixed list of problem shapes.
+
+    ``problems``: list of dicts with F, h, T, status (the forward solution),
+    dL_dT and dL_dF (output; problems may share one dL_dF tensor, whose result
+    is then the sum of their gradients)."""
+
+    def __init__(self, problems):
+        self.lib = load_library()
+        if not problems:
+            raise FmmError(FMM_EINVAL, "empty adjoint batch")
+        dt = problems[0]["F"].dtype
+        self.dtype = _dtype_code(dt)
+        n = len(problems)
+        arr = (FmmAdjointProblem * n)()
+        self.keep = []
+        for i, q in enumerate(problems):
+            F, T, st, gT, gF = q["F"], q["T"], q["status"], q["dL_dT"], q["dL_dF"]
+            shape = tuple(F.shape)
+            for name, t, want in (("T", T, torch.float64), ("status", st, torch.uint8),
+                                  ("dL_dT", gT, torch.float64), ("dL_dF", gF, torch.float64)):
+                if t.dtype != want or tuple(t.shape) != shape or not t.is_contiguous() or not t.is_cuda:
+                    raise FmmError(FMM_EINVAL, f"adjoint problem {i}: {name} must be a contiguous CUDA {want} "
+                                               f"tensor of shape {shape}")
+            if F.dtype != dt or not F.is_contiguous() or F.dim() != 3:
+                raise FmmError(FMM_EINVAL, f"adjoint problem {i}: F must be contiguous 3-D of the batch dtype")
+            self.keep += [F, T, st, gT, gF]
+            p = arr[i]
+            p.n0, p.n1, p.n2 = shape
+            p.h = float(q["h"])
+            p.F, p.T, p.status = F.data_ptr(), T.data_ptr(), st.data_ptr()
+            p.dL_dT, p.dL_dF = gT.data_ptr(), gF.data_ptr()
+        self.n = n
+        self.problems = arr
+        nbytes = int(self.lib.fmm_adjoint_workspace_bytes(n, arr))
+        if nbytes == 0:
+            raise FmmError(FMM_EINVAL, "invalid adjoint batch")
+        dev = problems[0]["F"].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+        self.nbytes = nbytes
+
+    def run(self, stream=None) -> None:
+        rc = self.lib.fmm_adjoint_batch(self.n, self.problems, self.dtype, _ptr(self.ws), self.nbytes,
+                                        _stream_handle(stream))
+        if rc != FMM_OK:
+            raise FmmError(rc, f"fmm_adjoint_batch: {strerror(rc)}")
+
+    def stats(self, stream=None, check=True) -> FmmAdjointStats:
+        st = FmmAdjointStats()
+        rc = self.lib.fmm_get_adjoint_stats(_ptr(self.ws), ctypes.byref(st), _stream_handle(stream))
+        if check and rc != FMM_OK:
+            raise FmmError(rc, f"adjoint failed on the device: {strerror(rc)}")
+        return st
+
+
+def adjoint(F, h, T, status, dL_dT):
+    """dL/dF (float64, F's shape) for one solved problem."""
+    gF = torch.empty(F.shape, dtype=torch.float64, device=F.device)
+    a = AdjointSolver([{"F": F, "h": h, "T": T, "status": status, "dL_dT": dL_dT.contiguous(), "dL_dF": gF}])
+    a.run()
+    a.stats()
+    return gF
+
+
+class Eikonal(torch.autograd.Function):
+    """T = solve(F) with the library's adjoint as backward: dL/dF from dL/dT.
+
+    ``forward(F, h, seed_idx, seed_val, band_width=inf, stride=None)`` returns
+    (T, status); status is not differentiable."""
+
+    @staticmethod
+    def forward(ctx, F, h, seed_idx, seed_val, band_width=math.inf, stride=None):
+        T, st, _ = solve(F.detach().contiguous(), h, seed_idx, seed_val, band_width=band_width, stride=stride)
+        ctx.save_for_backward(F, T, st)
+        ctx.h = float(h)
+        ctx.mark_non_differentiable(st)
+        return T, st
+
+    @staticmethod
+    def backward(ctx, gT, gst):
+        F, T, st = ctx.saved_tensors
+        g = adjoint(F.detach().contiguous(), ctx.h, T, st, gT.to(torch.float64).contiguous())
+        return g.to(F.dtype), None, None, None, None, None
+
+
+class EikonalShots(torch.autograd.Function):
+    """Many sources ("shots") over one speed model, solved as one batch: T has
+    shape (shots, n0, n1, n2), and the backward pass sums the shots'
+    gradients into one dL/dF inside the library.
+
+    ``forward(F, h, seeds, opts)``: seeds is a list of (seed_idx, seed_val);
+    opts a dict of BatchSolver options."""
+
+    @staticmethod
+    def forward(ctx, F, h, seeds, opts=None):
+        Fd = F.detach().contiguous()
+        S = len(seeds)
+        T = torch.empty((S,) + tuple(F.shape), dtype=torch.float64, device=F.device)
+        st = torch.empty((S,) + tuple(F.shape), dtype=torch.uint8, device=F.device)
+        probs = [{"F": Fd, "h": h, "seed_idx": i, "seed_val": v} for i, v in seeds]
+        b = BatchSolver(probs, T_out=[T[k] for k in range(S)], status_out=[st[k] for k in range(S)], **(opts or {}))
+        b.solve()
+        b.stats()
+        ctx.save_for_backward(Fd, T, st)
+        ctx.h = float(h)
+        ctx.mark_non_differentiable(st)
+        return T, st
+
+    @staticmethod
+    def backward(ctx, gT, gst):
+        F, T, st = ctx.saved_tensors
+        gT = gT.to(torch.float64).contiguous()
+        gF = torch.empty(F.shape, dtype=torch.float64, device=F.device)
+        a = AdjointSolver([{"F": F, "h": ctx.h, "T": T[k], "status": st[k], "dL_dT": gT[k], "dL_dF": gF}
+                           for k in range(T.shape[0])])
+        a.run()
+        a.stats()
+        return gF.to(F.dtype), None, None, None

@@ -192,3 +192,30 @@ def batch_problems(n_problems: int = 64, seed: int = 0, edge_range=(32, 192), co
                             torch.zeros(len(idx), dtype=torch.float64, device=device), math.inf,
                             {"seed": seed, "index": i, "sources": pts}))
     return out
+
+
+def tomography(n: int = 256, n_shots: int = 16, n_receivers: int = 1024, seed: int = 0, corr_len: float = 0.1,
+               amp: float = 0.3, perturb: float = 0.03, f_floor: float = 0.1, device="cpu") -> dict:
+    """A travel-time tomography setup on the n^3 unit cube (FP64): speed
+    F = max(1 + amp g, f_floor) with g a seeded Gaussian field; "observed"
+    travel times come from the perturbed model F_obs = max(1 + amp g +
+    perturb g', f_floor) with an independent field g'.  ``n_shots`` point
+    sources (T = 0) at distinct random points of the z = 0 face (axis 2
+    index 0), ``n_receivers`` distinct random points of the z = 1 face (axis 2
+    index n - 1), shared by all shots."""
+    g = gaussian_field(n, seed, corr_len, device=device).to(torch.float64)
+    g2 = gaussian_field(n, seed + 1, corr_len, device=device).to(torch.float64)
+    F = torch.clamp(1.0 + amp * g, min=f_floor).contiguous()
+    F_obs = torch.clamp(1.0 + amp * g + perturb * g2, min=f_floor).contiguous()
+    del g, g2
+    rng = np.random.default_rng(seed + 31337)
+    face = rng.choice(n * n, size=n_shots, replace=False)
+    shots = []
+    for f in face:
+        i0, i1 = divmod(int(f), n)
+        idx = torch.tensor([int(linear_index((n, n, n), i0, i1, 0))], dtype=torch.int64, device=device)
+        shots.append((idx, torch.zeros(1, dtype=torch.float64, device=device)))
+    rf = rng.choice(n * n, size=n_receivers, replace=False)
+    rec = np.array([linear_index((n, n, n), int(f) // n, int(f) % n, n - 1) for f in rf], dtype=np.int64)
+    return {"n": n, "h": 1.0 / (n - 1), "F": F, "F_obs": F_obs, "shots": shots,
+            "receivers": torch.from_numpy(rec).to(device), "seed": seed}

@@ -185,3 +185,44 @@ def test_tune_rejects_bad_candidates(fmm):
     bad_s = (ctypes.c_double * 1)(0.0)
     assert lib.fmm_tune_batch(1, good, fmm.FMM_F64, None, e, 1, bad_s, 1, 1, ws, 1 << 30, None,
                               ctypes.byref(best), None) == fmm.FMM_EINVAL
+
+
+# --------------------------------------------------------------------------
+# adjoint (host side)
+
+def test_adjoint_struct_layout(fmm, tmp_path):
+    src = tmp_path / "adj.c"
+    src.write_text('#include "fmm.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu\\n", sizeof(fmm_adjoint_problem),'
+                   ' offsetof(fmm_adjoint_problem, dL_dF), sizeof(fmm_adjoint_stats));return 0;}\n')
+    exe = tmp_path / "adj"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals == [ctypes.sizeof(fmm.FmmAdjointProblem), fmm.FmmAdjointProblem.dL_dF.offset,
+                    ctypes.sizeof(fmm.FmmAdjointStats)]
+
+
+def _adj_problems(fmm, shapes):
+    fake = 0x100000
+    arr = (fmm.FmmAdjointProblem * len(shapes))()
+    for p, sh in zip(arr, shapes):
+        p.n0, p.n1, p.n2 = sh
+        p.h = 0.1
+        p.F = p.T = p.status = p.dL_dT = p.dL_dF = fake
+    return arr
+
+
+def test_adjoint_workspace_and_rejects(fmm):
+    lib = fmm.load_library()
+    one = lib.fmm_adjoint_workspace_bytes(1, _adj_problems(fmm, [(10, 11, 12)]))
+    two = lib.fmm_adjoint_workspace_bytes(2, _adj_problems(fmm, [(10, 11, 12), (10, 11, 12)]))
+    assert one >= 29 * 1320 and two > one
+    assert lib.fmm_adjoint_workspace_bytes(1, _adj_problems(fmm, [(0, 4, 4)])) == 0
+    ws = ctypes.c_void_p(0x100000)
+    good = _adj_problems(fmm, [(8, 8, 8)])
+    assert lib.fmm_adjoint_batch(1, good, fmm.FMM_F64, ws, 64, None) == fmm.FMM_ENOMEM
+    for field, val in [("h", -1.0), ("T", None), ("status", None), ("dL_dT", None), ("dL_dF", None), ("F", None)]:
+        bad = _adj_problems(fmm, [(8, 8, 8)])
+        setattr(bad[0], field, val)
+        assert lib.fmm_adjoint_batch(1, bad, fmm.FMM_F64, ws, 1 << 30, None) == fmm.FMM_EINVAL, field
+    assert lib.fmm_adjoint_batch(1, good, 5, ws, 1 << 30, None) == fmm.FMM_EINVAL

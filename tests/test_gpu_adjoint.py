@@ -1,0 +1,235 @@
+"""GPU adjoint dL/dF through the C ABI.
+
+Bars: against the oracle's dense LU adjoint, max |g_gpu - g_oracle| <= 1e-9
+max |g_oracle| (both solve the same linear system exactly; the difference is
+rounding in the FP64 atomics' summation order and in the forward values);
+against central differences of the GPU forward solve at 20 cells of the
+256^3 tomography problem: with step 1e-5, 1e-6 relative; with step 1e-6, 1e-6
+relative plus that difference's disagreement with the step-1e-5 one.  A
+travel time carries a few ulps of rounding that change non-smoothly with F,
+about 1e-9 absolute in the loss difference over 2e-6, i.e. up to ~2e-6
+relative at step 1e-6 on this problem; at step 1e-5 it is ten times smaller.
+Cells where the one-sided slopes at step 1e-6 disagree by more than 1e-4 lie
+on a kink of the solution map and are skipped."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as oadj
+from paper_1502_07303_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_07303_amd import fmm as m
+    m.load_library()
+    return m
+
+
+def misfit_grad(T, rec, d):
+    Tr = T.reshape(-1)[rec]
+    g = np.zeros(T.size)
+    np.add.at(g, rec, 2.0 * (Tr - d))
+    return g.reshape(T.shape)
+
+
+def sphere_problem(n=16):
+    h = 1.0 / (n - 1)
+    x = np.arange(n) * h
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    phi = np.sqrt((X - 0.47) ** 2 + (Y - 0.52) ** 2 + (Z - 0.5) ** 2) - 0.36
+    s = np.sign(phi)
+    adj = np.zeros(phi.shape, dtype=bool)
+    for ax in range(3):
+        a = [slice(None)] * 3
+        b = [slice(None)] * 3
+        a[ax], b[ax] = slice(0, -1), slice(1, None)
+        ch = s[tuple(a)] != s[tuple(b)]
+        adj[tuple(a)] |= ch
+        adj[tuple(b)] |= ch
+    idx = np.flatnonzero(adj.reshape(-1)).astype(np.int64)
+    F = np.random.default_rng(5).uniform(0.7, 1.4, size=phi.shape)
+    return F, h, idx, phi.reshape(-1)[idx].copy()
+
+
+CASES = {
+    "random16": lambda: inputs.random_small((16, 16, 16), n_sources=2, seed=0).numpy() + (1.0 / 15,),
+    "ragged_barriers": lambda: inputs.random_small((9, 13, 11), n_sources=3, seed=4,
+                                                   zero_frac=0.08).numpy() + (1.0 / 12,),
+    "random16_f32": lambda: inputs.random_small((16, 14, 15), n_sources=1, seed=2,
+                                                dtype=torch.float32).numpy() + (1.0 / 15,),
+}
+
+
+def case_arrays(name):
+    if name == "sphere16":
+        F, h, idx, val = sphere_problem()
+        return F, idx, val, h
+    return CASES[name]()
+
+
+@pytest.mark.parametrize("name", ["random16", "ragged_barriers", "random16_f32", "sphere16"])
+def test_adjoint_matches_dense_oracle(fmm, oracle_mod, name):
+    F, idx, val, h = case_arrays(name)
+    dev = torch.device("cuda:0")
+    To, so, _, _ = oracle_mod.solve(F, h, idx, val)
+    rng = np.random.default_rng(11)
+    acc = np.flatnonzero((so.reshape(-1) & 3) == 2)
+    rec = rng.choice(acc, size=min(40, acc.size), replace=False)
+    d = To.reshape(-1)[rec] + 0.02 * rng.normal(size=rec.size)
+    gT = misfit_grad(To, rec, d)
+    g_or = oadj.dense_adjoint(F, h, To, so, gT)
+    Fd = torch.from_numpy(np.ascontiguousarray(F)).to(dev)
+    # (1) the adjoint kernel on the oracle's own forward solution
+    g1 = fmm.adjoint(Fd, h, torch.from_numpy(To).to(dev), torch.from_numpy(so).to(dev),
+                     torch.from_numpy(gT).to(dev)).cpu().numpy()
+    scale = np.max(np.abs(g_or))
+    assert scale > 0
+    assert np.max(np.abs(g1 - g_or)) <= 1e-12 * scale
+    # (2) the GPU forward solve followed by the GPU adjoint
+    Tg, sg, _ = fmm.solve(Fd, h, torch.from_numpy(idx).to(dev), torch.from_numpy(val).to(dev), time_limit_s=30)
+    assert np.array_equal(sg.cpu().numpy(), so)
+    gT2 = misfit_grad(Tg.cpu().numpy(), rec, d)
+    g2 = fmm.adjoint(Fd, h, Tg, sg, torch.from_numpy(gT2).to(dev)).cpu().numpy()
+    assert np.max(np.abs(g2 - g_or)) <= 1e-9 * scale
+
+
+def test_tomography_16_against_dense_oracle(fmm, oracle_mod):
+    """A 16^3 copy of the tomography configuration (shots on z = 0, receivers
+    on z = 1, squared misfit against a perturbed model): the shot-summed GPU
+    gradient against the sum of the oracle's dense adjoints."""
+    dev = torch.device("cuda:0")
+    tp = inputs.tomography(n=16, n_shots=4, n_receivers=60, seed=2)
+    h, rec = tp["h"], tp["receivers"].numpy()
+    F = tp["F"].numpy()
+    g_or = np.zeros(F.shape)
+    dobs = []
+    for idx, val in tp["shots"]:
+        To_obs, _, _, _ = oracle_mod.solve(tp["F_obs"].numpy(), h, idx.numpy(), val.numpy())
+        To, so, _, _ = oracle_mod.solve(F, h, idx.numpy(), val.numpy())
+        d = To_obs.reshape(-1)[rec]
+        dobs.append(d)
+        g_or += oadj.dense_adjoint(F, h, To, so, misfit_grad(To, rec, d))
+    Fg = tp["F"].to(dev).requires_grad_(True)
+    seeds = [(i.to(dev), v.to(dev)) for i, v in tp["shots"]]
+    T, _ = fmm.EikonalShots.apply(Fg, h, seeds)
+    dd = torch.from_numpy(np.stack(dobs)).to(dev)
+    L = ((T.reshape(len(seeds), -1)[:, torch.from_numpy(rec).to(dev)] - dd) ** 2).sum()
+    L.backward()
+    g = Fg.grad.cpu().numpy()
+    assert np.max(np.abs(g - g_or)) <= 1e-9 * np.max(np.abs(g_or))
+
+
+def test_adjoint_batch_shared_output_sums(fmm):
+    """Problems sharing one dL/dF buffer: the result is the sum of their
+    gradients; zero outside the system."""
+    dev = torch.device("cuda:0")
+    w = inputs.random_small((20, 18, 17), n_sources=1, seed=8)
+    F = w.F.to(dev)
+    shots = [(torch.tensor([i], dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.float64, device=dev))
+             for i in (0, 3001, 6119)]
+    sols = [fmm.solve(F, w.h, i, v, time_limit_s=30) for i, v in shots]
+    gTs = [torch.randn(F.shape, dtype=torch.float64, device=dev) for _ in shots]
+    singles = [fmm.adjoint(F, w.h, T, st, g) for (T, st, _), g in zip(sols, gTs)]
+    gF = torch.empty(F.shape, dtype=torch.float64, device=dev)
+    a = fmm.AdjointSolver([{"F": F, "h": w.h, "T": T, "status": st, "dL_dT": g, "dL_dF": gF}
+                           for (T, st, _), g in zip(sols, gTs)])
+    a.run()
+    st = a.stats()
+    assert st.n_points == 3 * (F.numel() - 1) and st.n_levels > 0
+    ref = singles[0] + singles[1] + singles[2]
+    assert torch.max(torch.abs(gF - ref)).item() <= 1e-12 * torch.max(torch.abs(ref)).item()
+    for (i, _), s in zip(shots, singles):
+        assert s.reshape(-1)[i].item() == 0.0
+
+
+def test_autograd_functions(fmm):
+    dev = torch.device("cuda:0")
+    w = inputs.random_small((18, 20, 16), n_sources=2, seed=6)
+    F = w.F.to(dev).requires_grad_(True)
+    T, st = fmm.Eikonal.apply(F, w.h, w.seed_idx.to(dev), w.seed_val.to(dev))
+    target = T.detach() * 1.01
+    loss = ((T - target) ** 2).sum()
+    loss.backward()
+    ref = fmm.adjoint(F.detach(), w.h, T.detach(), st, (2.0 * (T - target)).detach())
+    assert torch.max(torch.abs(F.grad - ref)).item() <= 1e-12 * ref.abs().max().item()
+    # several shots over one model: the same as the sum of single-shot gradients
+    F2 = w.F.to(dev).requires_grad_(True)
+    seeds = [(torch.tensor([k], dtype=torch.int64, device=dev), torch.zeros(1, dtype=torch.float64, device=dev))
+             for k in (5, 2500, 5000)]
+    Ts, sts = fmm.EikonalShots.apply(F2, w.h, seeds)
+    l2 = (Ts ** 2).sum()
+    l2.backward()
+    tot = torch.zeros_like(ref)
+    for k, (i, v) in enumerate(seeds):
+        Tk, sk, _ = fmm.solve(F2.detach(), w.h, i, v)
+        tot += fmm.adjoint(F2.detach(), w.h, Tk, sk, 2.0 * Tk)
+    assert torch.max(torch.abs(F2.grad - tot)).item() <= 1e-9 * tot.abs().max().item()
+
+
+def test_finite_differences_tomography_256(fmm):
+    """The 256^3 tomography configuration: 16 shots on the z = 0 face, 1024
+    receivers on z = 1, loss = sum of squared misfits against the travel times
+    of a perturbed model.  Adjoint vs central differences of the GPU forward
+    at 20 cells."""
+    dev = torch.device("cuda:0")
+    tp = inputs.tomography(n=256, n_shots=16, n_receivers=1024, seed=0, device=dev)
+    h, rec = tp["h"], tp["receivers"]
+
+    def forward(F):
+        T, st = fmm.EikonalShots.apply(F, h, tp["shots"], {"time_limit_s": 60})
+        return T, st
+
+    with torch.no_grad():
+        Tobs, _ = forward(tp["F_obs"])
+        dobs = Tobs.reshape(16, -1)[:, rec].clone()
+    F = tp["F"].clone().requires_grad_(True)
+    T, _ = forward(F)
+    L = ((T.reshape(16, -1)[:, rec] - dobs) ** 2).sum()
+    L.backward()
+    g = F.grad.reshape(-1).cpu().numpy()
+
+    def loss_at(Fv):
+        with torch.no_grad():
+            Tv, _ = forward(Fv)
+            return float(((Tv.reshape(16, -1)[:, rec] - dobs) ** 2).sum().item())
+
+    rng = np.random.default_rng(3)
+    big = np.flatnonzero(np.abs(g) > 1e-2 * np.abs(g).max())
+    cells = rng.choice(big, size=20, replace=False)
+    base = tp["F"]
+    used, worst6, worst5 = 0, 0.0, 0.0
+    for c in cells:
+        L = {}
+        for s in (-1e-5, -1e-6, 0.0, 1e-6, 1e-5):
+            Fp = base.clone()
+            Fp.view(-1)[int(c)] += s
+            L[s] = loss_at(Fp)
+        # step 1e-6: the central difference, and the one-sided slopes whose
+        # disagreement bounds its rounding noise (and flags a kink)
+        e = 1e-6
+        back, fwd = (L[0.0] - L[-e]) / e, (L[e] - L[0.0]) / e
+        c6 = (L[e] - L[-e]) / (2 * e)
+        if abs(fwd - back) > 1e-4 * abs(c6):
+            continue  # a kink of the solution map within the step
+        c5 = (L[1e-5] - L[-1e-5]) / 2e-5
+        used += 1
+        err6 = abs(g[c] - c6) / abs(c6)
+        err5 = abs(g[c] - c5) / abs(c5)
+        print(f"  cell {int(c)}: adjoint {g[c]:.12e} fd(1e-6) {c6:.12e} rel {err6:.2e} (noise "
+              f"{abs(fwd - back) / abs(c6):.1e}) fd(1e-5) rel {err5:.2e}", flush=True)
+        # step 1e-5 carries ten times less rounding noise: the strict bar; at
+        # step 1e-6 the bar is widened by that difference's own disagreement
+        # with the step-1e-5 one
+        assert err5 <= 1e-6, c
+        assert err6 <= 1e-6 + abs(c6 - c5) / abs(c6), c
+        worst6, worst5 = max(worst6, err6), max(worst5, err5)
+    print(f"tomography FD: {used} cells, worst relative error {worst6:.3e} (step 1e-6), "
+          f"{worst5:.3e} (step 1e-5)", flush=True)
+    assert used >= 15
