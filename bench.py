@@ -158,6 +158,62 @@ def batch_vs_serial(fmm, inputs, dev, steps, tune=True):
                       "(8^3 tiles, stride 2h) back to back"}
 
 
+def adjoint_vs_forward(fmm, inputs, dev, steps):
+    """The 256^3 tomography problem: 16 shots on the z = 0 face over one FP64
+    speed model 1 + 0.3 g, 1024 receivers on z = 1, squared misfit against a
+    perturbed model.  Forward = the 16-shot batched solve; adjoint = dL/dF of
+    all 16 shots summed into one gradient."""
+    tp = inputs.tomography(n=256, n_shots=16, n_receivers=1024, seed=0, device=dev)
+    S, n, h, rec = len(tp["shots"]), tp["n"], tp["h"], tp["receivers"]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        return best
+
+    def batch(F):
+        T = torch.empty((S, n, n, n), dtype=torch.float64, device=dev)
+        st = torch.empty((S, n, n, n), dtype=torch.uint8, device=dev)
+        b = fmm.BatchSolver([{"F": F, "h": h, "seed_idx": i, "seed_val": v} for i, v in tp["shots"]],
+                            T_out=[T[k] for k in range(S)], status_out=[st[k] for k in range(S)])
+        return b, T, st
+
+    bo, To, _ = batch(tp["F_obs"])
+    bo.solve()
+    bo.stats()
+    dobs = To.reshape(S, -1)[:, rec].clone()
+    del bo, To
+    b, T, st = batch(tp["F"])
+    ms_fwd = timed(b.solve, steps)
+    b.stats()
+    gT = torch.zeros((S, n ** 3), dtype=torch.float64, device=dev)
+    gT[:, rec] = 2.0 * (T.reshape(S, -1)[:, rec] - dobs)
+    gT = gT.reshape(S, n, n, n)
+    gF = torch.empty((n, n, n), dtype=torch.float64, device=dev)
+    a = fmm.AdjointSolver([{"F": tp["F"], "h": h, "T": T[k], "status": st[k], "dL_dT": gT[k], "dL_dF": gF}
+                           for k in range(S)])
+    ms_adj = timed(a.run, steps)
+    ast = a.stats()
+    loss = float(((T.reshape(S, -1)[:, rec] - dobs) ** 2).sum().item())
+    return {"config": "256^3 FP64 speed max(1 + 0.3 g, 0.1), 16 shots on the z=0 face (one batch), 1024 receivers "
+                      "on z=1, squared misfit against a perturbed model",
+            "forward_ms": round(ms_fwd, 3), "adjoint_ms": round(ms_adj, 3),
+            "adjoint_over_forward": round(ms_adj / ms_fwd, 4),
+            "equations": int(ast.n_points), "levels": int(ast.n_levels), "loss": loss,
+            "timing": "min over steps of HIP events; forward = fmm_solve_batch of the 16 shots (8^3 tiles, "
+                      "stride 2h), adjoint = fmm_adjoint_batch of the 16 shots into one dL/dF"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +226,7 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=352)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-serial measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward measurement")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GiB for a plain device copy, timed as achievable-HBM context and used to "
                          "calibrate HBM byte counters")
@@ -262,6 +319,13 @@ def main():
             f"(default {batch['batched_default_ms']}, graph {batch['graph_replay_ms']}), "
             f"speedup {batch['speedup']}x, tuned {batch['tuned']}")
 
+    adj = None
+    if not args.no_adjoint:
+        log("adjoint vs forward (256^3, 16 shots) ...")
+        adj = adjoint_vs_forward(fmm, inputs, dev, max(args.steps, 3))
+        log(f"  forward {adj['forward_ms']} ms, adjoint {adj['adjoint_ms']} ms "
+            f"({adj['adjoint_over_forward']}x), {adj['levels']} levels")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the oracle on a {args.cpu_crop}^3 crop ...")
@@ -291,6 +355,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_copy_probe": copy_probe,
         "batch_vs_serial": batch,
+        "adjoint_vs_forward": adj,
         "solve": {"accepted": n_acc, "points": N, "restarts": int(stats.n_restarts),
                   "tile_marches": int(stats.n_tile_marches), "solves": int(stats.n_solves),
                   "rounds": int(stats.n_rounds), "reopened": int(stats.n_reopened),

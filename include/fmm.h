@@ -247,8 +247,9 @@ int fmm_tune_batch(int64_t n_problems, const fmm_problem *problems, fmm_dtype F_
  * solution (T_out and status_out of fmm_solve or fmm_solve_batch), the
  * gradient of the loss with respect to T (entries outside the accepted set
  * are ignored) and the output.  All pointers are device pointers, row-major
- * (n0, n1, n2).  Several problems may share one dL_dF array: their gradients
- * are summed (e.g. many sources over one speed model). */
+ * (n0, n1, n2).  Several problems of the same grid may pass the same dL_dF
+ * pointer: their gradients are summed (e.g. many sources over one speed
+ * model); distinct dL_dF arrays must not overlap. */
 typedef struct {
     int64_t n0, n1, n2;
     double h;

@@ -37,7 +37,7 @@ struct AdjCtrl {
 struct AdjParams {
     AdjCtrl *ctrl;
     const AdjInst *inst;
-    double *acc;      // per point: S_p lambda_p being accumulated
+    double *acc;      // per point: S_p lambda_p being accumulated; once processed, its dL/dF term
     uint32_t *cnt;    // per point: dependents not yet processed
     uint8_t *code;    // per point: upwind set, 2 bits per axis
     uint64_t *list0, *list1;  // frontiers
@@ -47,6 +47,16 @@ constexpr int ADJ_PACK = 16;
 struct AdjPack {
     AdjInst v[ADJ_PACK];
     uint32_t first, n;
+};
+
+// Output gather: out[p] (accumulate ? += : =) sum over the m problems whose
+// points start at base[k] of their gradient terms.
+constexpr int ADJ_GATHER = 64;
+struct AdjGather {
+    double *out;
+    int64_t n;
+    int64_t base[ADJ_GATHER];
+    uint32_t m, accumulate;
 };
 
 // Workspace carving for `total` points over n problems.

@@ -28,6 +28,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "fmm_device.h"
 #include "fmm_adjoint.h"
@@ -87,7 +88,7 @@ __device__ __forceinline__ uint32_t upwind_code(const AdjInst &I, int64_t p, int
     return code;
 }
 
-// Reset: accumulators, counters, codes and the caller's dL/dF of every problem.
+// Reset: accumulators, counters and codes of every problem.
 __global__ void k_adj_zero(AdjParams P, AdjInst I)
 {
     const int64_t N = I.n0 * I.n1 * I.n2;
@@ -96,7 +97,6 @@ __global__ void k_adj_zero(AdjParams P, AdjInst I)
         P.acc[g] = 0.0;
         P.cnt[g] = 0u;
         P.code[g] = 0u;
-        I.dL_dF[p] = 0.0;
     }
 }
 
@@ -154,14 +154,64 @@ __global__ void k_adj_front0(AdjParams P, AdjInst I, uint32_t j)
     }
 }
 
-template <typename FT> __global__ void __launch_bounds__(256) k_adj_sweep(AdjParams P)
+#ifndef FMM_ADJ_WG_PER_CU
+#define FMM_ADJ_WG_PER_CU 1
+#endif
+#ifndef FMM_ADJ_BLOCK
+#define FMM_ADJ_BLOCK 256
+#endif
+constexpr int ADJ_BLOCK = FMM_ADJ_BLOCK;
+
+// Process one frontier point: its gradient term, its contributions to its
+// upwind points, and the upwind points whose last dependent it was join the
+// next frontier (read only after the barrier that ends this level, so every
+// contribution to them is complete).  New frontier entries are staged in LDS
+// and appended with one atomic per workgroup.
+template <typename FT>
+__device__ __forceinline__ void adj_point(const AdjParams &P, uint64_t it, bool active, uint64_t *s_items,
+                                          uint32_t *s_n)
 {
-    __shared__ uint32_t s_ok;
+    if (!active) return;
+    const uint32_t j = (uint32_t)(it >> 40);
+    const int64_t p = (int64_t)(it & ADJ_LOCAL_MASK);
+    const AdjInst &I = P.inst[j];
+    const int64_t g = I.base + p;
+    const double lt = __hip_atomic_load(&P.acc[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t code = P.code[g];
+    const double up = fabs(I.T[p]);
+    const double f = (double)((const FT *)I.F)[p];
+    const int64_t str[3] = {I.n1 * I.n2, I.n2, 1};
+    int64_t q[3];
+    double d[3];
+    double S = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+        const uint32_t cc = (code >> (2 * ax)) & 3u;
+        q[ax] = cc == 0 ? -1 : (cc == 1 ? p - str[ax] : p + str[ax]);
+        d[ax] = cc == 0 ? 0.0 : up - fabs(I.T[q[ax]]);
+        S += d[ax];
+    }
+    // this point's gradient term; its accumulator is not needed any more
+    P.acc[g] = -(I.h * I.h) / (f * f * f * S) * lt;
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+        if (q[ax] < 0) continue;
+        const int64_t gq = I.base + q[ax];
+        atomicAdd(&P.acc[gq], (d[ax] / S) * lt);
+        const uint32_t old = atomicSub(&P.cnt[gq], 1u);
+        if (old == 1u && P.code[gq] != 0) s_items[atomicAdd(s_n, 1u)] = ((uint64_t)j << 40) | (uint64_t)q[ax];
+    }
+}
+
+template <typename FT> __global__ void __launch_bounds__(ADJ_BLOCK) k_adj_sweep(AdjParams P)
+{
+    __shared__ uint32_t s_ok, s_n;
+    __shared__ unsigned long long s_base;
+    __shared__ uint64_t s_items[3 * ADJ_BLOCK];
     AdjCtrl *c = P.ctrl;
     const uint32_t nwg = gridDim.x;
     uint32_t gen = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) c->nwg = nwg;
-    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t nth = (uint64_t)gridDim.x * blockDim.x;
     uint32_t level = 0;
     for (;;) {
@@ -173,51 +223,37 @@ template <typename FT> __global__ void __launch_bounds__(256) k_adj_sweep(AdjPar
         const uint64_t *cur = (level & 1) ? P.list1 : P.list0;
         uint64_t *nxt = (level & 1) ? P.list0 : P.list1;
         unsigned long long *nlen = &c->len[(level + 1) % 3];
-        const unsigned long long n_iter = (n + 63) / 64 * 64;
-        for (unsigned long long k = tid; k < n_iter; k += nth) {
-            bool want[3] = {false, false, false};
-            uint64_t item[3] = {0, 0, 0};
-            if (k < n) {
-                const uint64_t it = cur[k];
-                const uint32_t j = (uint32_t)(it >> 40);
-                const int64_t p = (int64_t)(it & ADJ_LOCAL_MASK);
-                const AdjInst &I = P.inst[j];
-                const int64_t g = I.base + p;
-                const double lt = __hip_atomic_load(&P.acc[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t code = P.code[g];
-                const double up = fabs(I.T[p]);
-                const double f = (double)((const FT *)I.F)[p];
-                const int64_t str[3] = {I.n1 * I.n2, I.n2, 1};
-                int64_t q[3];
-                double d[3];
-                double S = 0.0;
-#pragma unroll
-                for (int ax = 0; ax < 3; ax++) {
-                    const uint32_t cc = (code >> (2 * ax)) & 3u;
-                    q[ax] = cc == 0 ? -1 : (cc == 1 ? p - str[ax] : p + str[ax]);
-                    d[ax] = cc == 0 ? 0.0 : up - fabs(I.T[q[ax]]);
-                    S += d[ax];
-                }
-                atomicAdd(&I.dL_dF[p], -(I.h * I.h) / (f * f * f * S) * lt);
-#pragma unroll
-                for (int ax = 0; ax < 3; ax++) {
-                    if (q[ax] < 0) continue;
-                    const int64_t gq = I.base + q[ax];
-                    atomicAdd(&P.acc[gq], (d[ax] / S) * lt);
-                    const uint32_t old = atomicSub(&P.cnt[gq], 1u);
-                    if (old == 1u && P.code[gq] != 0) {
-                        want[ax] = true;
-                        item[ax] = ((uint64_t)j << 40) | (uint64_t)q[ax];
-                    }
-                }
-            }
-#pragma unroll
-            for (int ax = 0; ax < 3; ax++) push_item(want[ax], item[ax], nlen, nxt);
+        // the pass count is uniform within a workgroup (barriers inside)
+        for (unsigned long long k0 = (unsigned long long)blockIdx.x * blockDim.x; k0 < n; k0 += nth) {
+            if (threadIdx.x == 0) s_n = 0;
+            __syncthreads();
+            const unsigned long long k = k0 + threadIdx.x;
+            adj_point<FT>(P, k < n ? cur[k] : 0, k < n, s_items, &s_n);
+            __syncthreads();
+            const uint32_t m = s_n;
+            if (threadIdx.x == 0 && m) s_base = atomicAdd(nlen, (unsigned long long)m);
+            __syncthreads();
+            for (uint32_t t = threadIdx.x; t < m; t += blockDim.x) nxt[s_base + t] = s_items[t];
+            __syncthreads();
         }
         level++;
         if (!grid_sync(&c->bar, &c->abort, &c->error, ADJ_ERR_BARRIER, gen, nwg, &s_ok)) break;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) c->levels = level;
+}
+
+// dL/dF of one output array: the sum of the gradient terms of the problems
+// that share it (a point outside a problem's system contributes 0).
+__global__ void k_adj_gather(AdjParams P, AdjGather G)
+{
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < G.n; p += (int64_t)gridDim.x * blockDim.x) {
+        double s = G.accumulate ? G.out[p] : 0.0;
+        for (uint32_t k = 0; k < G.m; k++) {
+            const int64_t g = G.base[k] + p;
+            if (P.code[g]) s += P.acc[g];
+        }
+        G.out[p] = s;
+    }
 }
 
 __global__ void k_adj_init(AdjParams P, uint32_t n_inst)
@@ -291,11 +327,11 @@ template <typename FT> static hipError_t launch_adjoint_t(const AdjParams &P, co
     auto kern = k_adj_sweep<FT>;
     if (occ < 0) {
         int nb = 0;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0)) != hipSuccess) return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, ADJ_BLOCK, 0)) != hipSuccess) return e;
         occ = nb;
     }
     if (occ <= 0) return hipErrorInvalidConfiguration;
-    const unsigned grid = (unsigned)(std::min(occ, 4) * cus);
+    const unsigned grid = (unsigned)(std::min(occ, FMM_ADJ_WG_PER_CU) * cus);
     AdjParams Pc = P;
     void *args[] = {&Pc};
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -303,10 +339,37 @@ template <typename FT> static hipError_t launch_adjoint_t(const AdjParams &P, co
     if (cs == hipStreamCaptureStatusActive) {
         // a graph node: the grid is at most one occupancy wave and runs after
         // its predecessors, so its workgroups are resident together
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, Pc);
-        return hipGetLastError();
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(ADJ_BLOCK), 0, s, Pc);
+        e = hipGetLastError();
+    } else {
+        e = hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(ADJ_BLOCK), args, 0, s);
     }
-    return hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(256), args, 0, s);
+    if (e != hipSuccess) return e;
+    // gather each output array over the problems that share it
+    std::vector<bool> done((size_t)n, false);
+    for (int64_t j = 0; j < n; j++) {
+        if (done[(size_t)j]) continue;
+        AdjGather G;
+        memset(&G, 0, sizeof G);
+        G.out = insts[j].dL_dF;
+        G.n = insts[j].n0 * insts[j].n1 * insts[j].n2;
+        for (int64_t k = j; k < n; k++) {
+            if (done[(size_t)k] || insts[k].dL_dF != G.out) continue;
+            done[(size_t)k] = true;
+            G.base[G.m++] = insts[k].base;
+            if (G.m == ADJ_GATHER) {
+                hipLaunchKernelGGL(k_adj_gather, dim3(blocks_for(insts[j])), dim3(256), 0, s, P, G);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                G.accumulate = 1;
+                G.m = 0;
+            }
+        }
+        if (G.m) {
+            hipLaunchKernelGGL(k_adj_gather, dim3(blocks_for(insts[j])), dim3(256), 0, s, P, G);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_adjoint(const AdjParams &P, const AdjInst *insts, int64_t n, bool f64, hipStream_t s)

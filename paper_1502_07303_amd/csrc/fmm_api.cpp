@@ -440,6 +440,13 @@ int fmm_adjoint_batch(int64_t n_problems, const fmm_adjoint_problem *problems, f
     if (((uintptr_t)workspace & 255u) != 0) return FMM_EINVAL;
     for (int64_t i = 0; i < n_problems; i++)
         if (!adj_problem_ok(problems[i])) return FMM_EINVAL;
+    // problems that share an output array must have the same grid
+    std::unordered_map<const void *, int64_t> out_owner;
+    for (int64_t i = 0; i < n_problems; i++) {
+        auto it = out_owner.emplace(problems[i].dL_dF, i).first;
+        const fmm_adjoint_problem &a = problems[it->second], &b = problems[i];
+        if (a.n0 != b.n0 || a.n1 != b.n1 || a.n2 != b.n2) return FMM_EINVAL;
+    }
     std::vector<AdjInst> insts((size_t)n_problems);
     const uint64_t total = adj_total(n_problems, problems, &insts);
     if (total >= (1ull << 40)) return FMM_EINVAL;
