@@ -3,7 +3,8 @@
 
 Default workload: the 1024^3 full-domain march with an FP32 random speed field
 (F = clip(exp(0.5 g), 0.25, 4), g a Gaussian field with correlation length
-0.05) and four point sources, FP64 arithmetic, restart stride 2h, 8^3 tiles.
+0.05) and four point sources, FP64 arithmetic, 8^3 tiles, the restart stride
+swept by the library's autotuner (2h to 5h by default).
 Prints one JSON line: accepted grid points per second of the whole solve with
 inputs resident in HBM, the roofline of the restart driver (the dominant
 kernel) and a CPU baseline from the oracle on a bounded sample.
@@ -35,9 +36,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def read_traffic(kernel_tag):
+def read_traffic(kernel_tag, stride_h):
     """HBM bytes per driver launch from the committed rocprofv3 counter summary,
-    if it was taken with the current kernel build (tag match); else None."""
+    if it was taken with the current kernel build (tag match) at the same
+    restart stride; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -47,6 +49,11 @@ def read_traffic(kernel_tag):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_tag") != kernel_tag:
+        return None
+    try:
+        if float(vals.get("stride_h", "nan")) != float(stride_h):
+            return None
+    except ValueError:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -220,7 +227,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--stride-h", type=float, default=2.0, help="restart stride in units of h (inf allowed)")
+    ap.add_argument("--stride-h", type=float, default=None,
+                    help="restart stride in units of h (inf allowed); default: swept by the library's autotuner")
+    ap.add_argument("--sweep", default="2,3,4,5", help="strides (units of h) the autotuner tries")
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-crop", type=int, default=352)
@@ -265,7 +274,21 @@ def main():
     torch.cuda.synchronize()
     log(f"  generated in {time.perf_counter() - t0:.1f}s; sources {w.meta['sources']}")
     N = w.F.numel()
-    stride = args.stride_h * w.h
+    sweep = None
+    stride_h = args.stride_h
+    if stride_h is None:
+        # the restart stride is swept (Alg. 16's delta-s) by the library's autotuner
+        cand = [float(x) for x in args.sweep.split(",")]
+        t0 = time.perf_counter()
+        tb = fmm.BatchSolver([{"F": w.F, "h": w.h, "seed_idx": w.seed_idx, "seed_val": w.seed_val}],
+                             tile_edge=args.tile, with_status=False)
+        ms = tb.tune(edges=(args.tile,), strides_h=cand, reps=1)
+        stride_h = float(tb.opts.stride_h)
+        sweep = {f"{sh:g}h": round(v, 3) for (_, sh), v in ms.items()}
+        del tb
+        torch.cuda.empty_cache()
+        log(f"  stride sweep {sweep} -> {stride_h:g}h ({time.perf_counter() - t0:.1f}s)")
+    stride = stride_h * w.h
     solver = fmm.Solver(w.shape, w.seed_idx.numel(), w.h, band_width=w.width, stride=stride,
                         tile_edge=args.tile, timing=True, device=dev, speed_dtype=w.F.dtype)
     T = torch.empty(w.shape, dtype=torch.float64, device=dev)
@@ -300,7 +323,7 @@ def main():
     alg_bytes = bytes_per_pt * n_acc
     achieved = alg_bytes / (ms_drv / 1e3) / 1e9
     tag = kernel_tag()
-    traffic = read_traffic(tag)
+    traffic = read_traffic(tag, stride_h)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "k_driver (restart loop: tile marches + exchange)",
@@ -349,7 +372,8 @@ def main():
                                "FP32 speed clip(exp(0.5 g), 0.25, 4), Gaussian g with correlation length 0.05, "
                                "4 point sources",
                    "n": args.n, "h": w.h, "speed_dtype": "f32", "sources": len(w.meta["sources"]),
-                   "band_width": "inf", "stride_h": args.stride_h, "tile_edge": args.tile, "seed": args.seed,
+                   "band_width": "inf", "stride_h": stride_h, "stride_sweep_ms": sweep, "tile_edge": args.tile,
+                   "seed": args.seed,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -77,12 +77,12 @@ template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int 
 }
 
 // Wavefronts per workgroup of the 8^3-tile driver (one workgroup per CU; LDS
-// bounds it at 10 for FP32 speeds and 9 for FP64).
+// bounds it at 12 for FP32 speeds and 10 for FP64).
 #ifndef FMM_E8_WAVES_F32
-#define FMM_E8_WAVES_F32 10
+#define FMM_E8_WAVES_F32 12
 #endif
 #ifndef FMM_E8_WAVES_F64
-#define FMM_E8_WAVES_F64 9
+#define FMM_E8_WAVES_F64 10
 #endif
 
 constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
@@ -94,7 +94,7 @@ enum { MODE_INIT = 0, MODE_M1 = 1, MODE_M2 = 2 };
 template <int E, typename FT> struct WaveLds {
     double T[Geo<E>::DV];                 // domain values (interior + face halos)
     FT F[Geo<E>::V];                      // interior speeds
-    uint16_t list[2][Geo<E>::V];          // candidate lists (interior indices)
+    uint16_t list[Geo<E>::V];             // candidate list (interior indices)
     alignas(8) uint8_t cf[Geo<E>::V];     // candidate flags (interior indices)
     uint8_t fl[Geo<E>::DV];               // FL_* per domain cell
     uint32_t stL[STAGE];                  // staged live-list appends
@@ -323,8 +323,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
 {
     using G = Geo<E>;
     const int lane = threadIdx.x & 63;
-    int cur = 0;
-    int n = compact(L, L.list[0]);
+    int n = compact(L, L.list);
     int rounds = 0;
     while (n > 0) {
         if (++rounds > MAX_ROUNDS) {
@@ -338,7 +337,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             bool ch = false;
             int p = 0;
             if (k < n) {
-                p = L.list[cur][k];
+                p = L.list[k];
                 ch = eval_point(L, p, h, th, nv, vp, na, upd);
                 ws.n_solve++;
             }
@@ -360,8 +359,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             }
             wave_sync();
         }
-        cur ^= 1;
-        n = compact(L, L.list[cur]);
+        n = compact(L, L.list);
     }
     return rounds;
 }
