@@ -219,3 +219,63 @@ def tomography(n: int = 256, n_shots: int = 16, n_receivers: int = 1024, seed: i
     rec = np.array([linear_index((n, n, n), int(f) // n, int(f) % n, n - 1) for f in rf], dtype=np.int64)
     return {"n": n, "h": 1.0 / (n - 1), "F": F, "F_obs": F_obs, "shots": shots,
             "receivers": torch.from_numpy(rec).to(device), "seed": seed}
+
+
+def _signed_seeds(phi: np.ndarray):
+    """Seeds of an interface given by the sign of phi: the points with phi = 0
+    or with a 6-neighbour of the opposite sign, valued phi (Alg. 1/8)."""
+    s = np.sign(phi)
+    adj = s == 0
+    for ax in range(3):
+        a = [slice(None)] * 3
+        b = [slice(None)] * 3
+        a[ax], b[ax] = slice(0, -1), slice(1, None)
+        ch = s[tuple(a)] * s[tuple(b)] < 0
+        adj[tuple(a)] |= ch
+        adj[tuple(b)] |= ch
+    idx = np.flatnonzero(adj.reshape(-1)).astype(np.int64)
+    return idx, phi.reshape(-1)[idx].astype(np.float64).copy()
+
+
+def paper_case(case: int, n: int = 64, device="cpu") -> Workload:
+    """The paper's six test problems (Sec. 5.1) on an n^3 node grid over its
+    domain [-0.5, 0.5]^3 (h = 1/(n-1)), FP64, full march:
+
+    1. sphere of radius 0.25 at the centre, interior negative (two-sided);
+    2. plane 100x + y + 2z = 0, positive where 100x + y + 2z > 0 (two-sided);
+    3-5. point source at the centre with F from Eqs. 13, 14, 15;
+    6. point source at the centre, F = 0 inside the four perforated spherical
+       shells of Eq. 16 (w = 1/24) and 1 elsewhere.
+
+    Interfaces are seeded with their exact signed distance at the points next
+    to a sign change; the point source is the grid point nearest the centre
+    (index n // 2 per axis), T = 0."""
+    h = 1.0 / (n - 1)
+    x = -0.5 + np.arange(n) * h
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    F = np.ones((n, n, n))
+    if case == 1:
+        idx, val = _signed_seeds(np.sqrt(X ** 2 + Y ** 2 + Z ** 2) - 0.25)
+    elif case == 2:
+        idx, val = _signed_seeds((100.0 * X + Y + 2.0 * Z) / math.sqrt(100.0 ** 2 + 1.0 + 4.0))
+    elif case in (3, 4, 5, 6):
+        c = n // 2
+        idx = np.array([linear_index((n, n, n), c, c, c)], dtype=np.int64)
+        val = np.zeros(1)
+        if case == 4:
+            F = 1.0 + 0.50 * np.sin(20 * np.pi * X) * np.sin(20 * np.pi * Y) * np.sin(20 * np.pi * Z)
+        elif case == 5:
+            F = 1.0 - 0.99 * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y) * np.sin(2 * np.pi * Z)
+        elif case == 6:
+            w = 1.0 / 24.0
+            R = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+            r = np.sqrt(X ** 2 + Y ** 2)
+            shells = [(0.15, 0.05, Z < 0), (0.25, 0.10, Z > 0), (0.35, 0.10, Z < 0), (0.45, 0.10, Z > 0)]
+            for r0, hole, side in shells:
+                F[(R > r0) & (R < r0 + w) & ~((r < hole) & side)] = 0.0
+            F.reshape(-1)[idx] = 1.0
+    else:
+        raise ValueError("case must be 1..6")
+    return Workload(f"paper_case{case}_{n}", torch.from_numpy(np.ascontiguousarray(F)).to(device), h,
+                    torch.from_numpy(idx).to(device), torch.from_numpy(val).to(device), math.inf,
+                    {"case": case})

@@ -1,0 +1,93 @@
+"""The paper's six test problems (Sec. 5.1) on the GPU, and the restart-count
+behaviour its driver study reports (Sec. 5.3-5.5).
+
+Parity bar as everywhere: identical status bytes, max |dT| <= 1e-12 max|T|
+against the oracle.  The restart-count checks are the paper's qualitative
+statements, with loose bounds; the measured counts are printed."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import parity_report
+from paper_1502_07303_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1502_07303_amd import fmm as m
+    m.load_library()
+    return m
+
+
+def gpu(fmm, w, **kw):
+    dev = torch.device("cuda:0")
+    kw.setdefault("time_limit_s", 60)
+    T, st, stats = fmm.solve(w.F.to(dev), w.h, w.seed_idx.to(dev), w.seed_val.to(dev), **kw)
+    return T.cpu().numpy(), st.cpu().numpy(), stats
+
+
+@pytest.mark.parametrize("case", [1, 2, 3, 4, 5, 6])
+def test_paper_case_parity(fmm, oracle_mod, case):
+    w = inputs.paper_case(case, n=48)
+    F, idx, val = w.numpy()
+    To, so, sto, _ = oracle_mod.solve(F, w.h, idx, val)
+    for stride_h in (0.5, 2.0, math.inf):
+        Tg, sg, st = gpu(fmm, w, stride=stride_h * w.h)
+        rep = parity_report(Tg, sg, To, so)
+        assert rep["same_status"], (stride_h, rep)
+        assert rep["rel"] <= TOL, (stride_h, rep)
+        assert st.n_accepted == sto.n_accepted
+
+
+def test_restarts_scale_inversely_with_stride(fmm):
+    """Sec. 5.3/5.5: each restart advances the band bound by the stride, so the
+    restart count is about max T / stride (plus the two restarts that start
+    and end the loop)."""
+    w = inputs.paper_case(3, n=64)
+    out = {}
+    for k in (1.0, 2.0, 4.0):
+        _, _, st = gpu(fmm, w, stride=k * w.h)
+        out[k] = (st.n_restarts, st.max_abs_T)
+    print("case 3, 64^3, restarts by stride:", {k: v[0] for k, v in out.items()}, flush=True)
+    for k, (nr, tmax) in out.items():
+        ratio = nr * k * w.h / tmax
+        assert 0.9 <= ratio <= 1.3, (k, nr, ratio)
+    assert out[1.0][0] > out[2.0][0] > out[4.0][0]
+
+
+def test_restarts_at_infinite_stride_follow_the_decomposition(fmm):
+    """Sec. 5.3: with an infinite stride every subdomain is marched to
+    completion when triggered, and the restart count follows how many
+    subdomains the front must cross: one subdomain needs 2, and finer
+    decompositions need more."""
+    w = inputs.paper_case(3, n=64)
+    nr = {}
+    for e in (16, 8, 4):
+        _, _, st = gpu(fmm, w, stride=math.inf, tile_edge=e)
+        nr[e] = st.n_restarts
+    print("case 3, 64^3, stride inf, restarts by tile edge:", nr, flush=True)
+    assert nr[16] < nr[8] < nr[4]
+    one = inputs.paper_case(3, n=16)
+    _, _, st = gpu(fmm, one, stride=math.inf, tile_edge=16)
+    assert st.n_restarts == 2
+
+
+def test_restarts_grow_with_travel_time(fmm):
+    """Sec. 5.4: the barriers of case 6 and the slow regions of case 5 make
+    travel times longer, hence more restarts at a given stride than the
+    unity-speed point source of case 3."""
+    nr = {}
+    for case in (3, 5, 6):
+        w = inputs.paper_case(case, n=64)
+        _, _, st = gpu(fmm, w, stride=2.0 * w.h)
+        nr[case] = st.n_restarts
+    print("64^3, stride 2h, restarts by case:", nr, flush=True)
+    assert nr[5] > nr[3] and nr[6] > nr[3]
