@@ -44,7 +44,9 @@ def _load():
     lib.oracle_godunov_batch.argtypes = [P, P, P, i64]
     lib.oracle_godunov_batch.restype = None
     lib.oracle_solve.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, i64, dbl, P, P, P, i64,
-                                 ctypes.POINTER(OracleStats)]
+                                 ctypes.POINTER(OracleStats), P]
+    lib.oracle_godunov_w.argtypes = [dbl, dbl, dbl, dbl, dbl, dbl, dbl, ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_godunov_w.restype = dbl
     lib.oracle_solve.restype = ctypes.c_int
     lib.oracle_sweep.argtypes = [i64, i64, i64, dbl, P, P, P, i64, P, i64]
     lib.oracle_sweep.restype = i64
@@ -68,6 +70,14 @@ def godunov_k(a1, a2, a3, r):
     return u, k.value
 
 
+def godunov_w(a1, a2, a3, s1, s2, s3, r):
+    """(G, k) with per-axis spacing factors s (weights 1 / s^2)."""
+    k = ctypes.c_int(0)
+    u = _load().oracle_godunov_w(float(a1), float(a2), float(a3), float(s1), float(s2), float(s3), float(r),
+                                 ctypes.byref(k))
+    return u, k.value
+
+
 def godunov_batch(a, r):
     """Vectorised G over an (n, 3) array of upwind values and n values of r."""
     a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1, 3)
@@ -77,11 +87,12 @@ def godunov_batch(a, r):
     return out
 
 
-def solve(F, h, seed_idx, seed_val, width=np.inf, record_order=False):
+def solve(F, h, seed_idx, seed_val, width=np.inf, record_order=False, axis_scale=None):
     """Sequential narrow-band FMM on the grid ``F.shape`` (C order, axis 2 fastest).
 
-    Returns ``(T, status, stats, order)``; ``order`` lists the accepted points
-    in pop order when ``record_order`` is set.
+    ``axis_scale`` (3 positive factors, optional): grid spacing h * s_a along
+    axis a.  Returns ``(T, status, stats, order)``; ``order`` lists the
+    accepted points in pop order when ``record_order`` is set.
     """
     lib = _load()
     F = np.ascontiguousarray(F)
@@ -96,12 +107,13 @@ def solve(F, h, seed_idx, seed_val, width=np.inf, record_order=False):
     T = np.empty(F.shape, dtype=np.float64)
     status = np.empty(F.shape, dtype=np.uint8)
     order = np.full(N, -1, dtype=np.int64) if record_order else None
+    sc = None if axis_scale is None else np.ascontiguousarray(axis_scale, dtype=np.float64).reshape(3)
     st = OracleStats()
     rc = lib.oracle_solve(n0, n1, n2, float(h), _ptr(F), int(F.dtype == np.float64),
                           _ptr(seed_idx) if len(seed_idx) else None,
                           _ptr(seed_val) if len(seed_val) else None, len(seed_idx), float(width),
                           _ptr(T), _ptr(status), _ptr(order), N if record_order else 0,
-                          ctypes.byref(st))
+                          ctypes.byref(st), _ptr(sc))
     if rc != 0:
         raise RuntimeError(f"oracle_solve failed with code {rc}")
     if record_order:

@@ -23,6 +23,10 @@ with dL/du_p = sign(T_p) dL/dT_p.  This module builds A as a dense N x N
 matrix and solves the transposed system by LU (numpy.linalg.solve): plain and
 slow, for grids of a few thousand points.
 
+Per-axis spacing h s_a (the paper allows Delta x, Delta y, Delta z to
+differ, Sec. 2.1) weights each term by w = 1 / s_a^2, in the equation and in
+its linearisation alike.
+
 Readings this module fixes:
   - the upwind candidates of p are the accepted or seed neighbours on p's side
     with |T_q| < |T_p| (the final values; Alg. 11's filter);
@@ -32,12 +36,13 @@ Readings this module fixes:
 """
 import numpy as np
 
-from . import ST_ACCEPTED, ST_NEG, ST_SEED, _load, godunov_k
+from . import ST_ACCEPTED, ST_NEG, ST_SEED, _load, godunov_k, godunov_w
 
 
-def upwind_sets(F, h, T, status):
+def upwind_sets(F, h, T, status, axis_scale=None):
     """Per accepted non-seed point: list of (neighbour linear index) in U_p.
 
+    ``axis_scale``: per-axis spacing factors (grid spacing h * s_a), or None.
     Returns a dict {p: [q, ...]} over linear indices (C order)."""
     _load()
     n0, n1, n2 = T.shape
@@ -66,29 +71,36 @@ def upwind_sets(F, h, T, status):
                 if v < up and v < best_v:
                     best_q, best_v = q, v
             per_axis.append((best_v, ax, best_q))
-        u, k = godunov_k(per_axis[0][0], per_axis[1][0], per_axis[2][0], h / Ff[p])
+        if axis_scale is None:
+            u, k = godunov_k(per_axis[0][0], per_axis[1][0], per_axis[2][0], h / Ff[p])
+        else:
+            u, k = godunov_w(per_axis[0][0], per_axis[1][0], per_axis[2][0], *axis_scale, h / Ff[p])
         chosen = sorted(per_axis, key=lambda t: (t[0], t[1]))[:k]
-        out[p] = [q for _, _, q in chosen]
+        out[p] = [(q, ax) for _, ax, q in chosen]
     return out
 
 
-def dense_adjoint(F, h, T, status, dL_dT):
+def dense_adjoint(F, h, T, status, dL_dT, axis_scale=None):
     """dL/dF for a loss whose gradient with respect to T is ``dL_dT``.
 
-    Zero at seeds, at points outside the accepted set and where F <= 0."""
+    With per-axis spacing h s_a the equation of p is sum_{q in U_p} w_q
+    (u_p - u_q)^2 = (h / F_p)^2, w = 1 / s_a^2 for the axis of q, and its
+    linearisation carries the same weights.  Zero at seeds, at points
+    outside the accepted set and where F <= 0."""
     F = np.asarray(F)
     T = np.asarray(T, dtype=np.float64)
     N = T.size
-    sets = upwind_sets(F, h, T, status)
+    sets = upwind_sets(F, h, T, status, axis_scale)
+    w = [1.0, 1.0, 1.0] if axis_scale is None else [1.0 / (s * s) for s in axis_scale]
     Tf = np.abs(T.reshape(-1))
     Ff = F.reshape(-1).astype(np.float64)
     A = np.eye(N)
     B = np.zeros(N)
     for p, U in sets.items():
-        S = sum(Tf[p] - Tf[q] for q in U)
+        S = sum(w[ax] * (Tf[p] - Tf[q]) for q, ax in U)
         A[p, p] = S
-        for q in U:
-            A[p, q] = -(Tf[p] - Tf[q])
+        for q, ax in U:
+            A[p, q] = -w[ax] * (Tf[p] - Tf[q])
         B[p] = -(h * h) / (Ff[p] ** 3)
     sign = np.where(T.reshape(-1) < 0.0, -1.0, 1.0)
     g = np.zeros(N)

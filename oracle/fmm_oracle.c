@@ -132,6 +132,55 @@ double oracle_godunov(double x, double y, double z, double r)
     return oracle_godunov_k(x, y, z, r, &k);
 }
 
+/* Local solver on a grid with per-axis spacing h_i = h s_i (the paper's
+ * Delta x, Delta y, Delta z, Sec. 2.1): with weights w_i = 1 / s_i^2 and
+ * r = h / F the upwind equation is sum_i w_i max(u - a_i, 0)^2 = r^2.  For the
+ * k smallest values (sorted together with their weights) its roots are
+ *   k=1: u1 = a1 + r s1
+ *   k=2: D2 = (w1+w2) r^2 - (w1 w2) (a2-a1)^2,
+ *        u2 = ((w1 a1 + w2 a2) + sqrt(D2)) / (w1+w2)
+ *   k=3: D3 = ((w1+w2)+w3) r^2 - (((w1 w2)(a2-a1)^2 + (w1 w3)(a3-a1)^2) + (w2 w3)(a3-a2)^2),
+ *        u3 = (((w1 a1 + w2 a2) + w3 a3) + sqrt(D3)) / ((w1+w2)+w3)
+ * (the identity (sum w a)^2 - (sum w)(sum w a^2) = -sum_{i<j} w_i w_j (a_i-a_j)^2
+ * again removes the cancellation), with the same causality rule and minimum.
+ * With all s_i = 1 every operation reduces to the one of oracle_godunov(), so
+ * the two agree bit for bit. */
+double oracle_godunov_w(double x, double y, double z, double sx, double sy, double sz, double r, int *k)
+{
+    double a[3] = {x, y, z}, sc[3] = {sx, sy, sz};
+    /* sort the values, carrying each axis' scale along (stable) */
+    for (int i = 1; i < 3; i++)
+        for (int j = i; j > 0 && a[j - 1] > a[j]; j--) {
+            double t = a[j]; a[j] = a[j - 1]; a[j - 1] = t;
+            t = sc[j]; sc[j] = sc[j - 1]; sc[j - 1] = t;
+        }
+    double a1 = a[0], a2 = a[1], a3 = a[2];
+    double w1 = 1.0 / (sc[0] * sc[0]), w2 = 1.0 / (sc[1] * sc[1]), w3 = 1.0 / (sc[2] * sc[2]);
+    *k = 0;
+    if (!(a1 < INFINITY)) return INFINITY;
+    double r2 = r * r;
+    double best = a1 + r * sc[0];
+    *k = 1;
+    if (a2 < INFINITY) {
+        double d12 = a2 - a1;
+        double D2 = (w1 + w2) * r2 - (w1 * w2) * (d12 * d12);
+        if (D2 >= 0.0) {
+            double u2 = ((w1 * a1 + w2 * a2) + sqrt(D2)) / (w1 + w2);
+            if (u2 > a2 && u2 < best) { best = u2; *k = 2; }
+        }
+        if (a3 < INFINITY) {
+            double d13 = a3 - a1, d23 = a3 - a2;
+            double D3 = ((w1 + w2) + w3) * r2 -
+                        (((w1 * w2) * (d12 * d12) + (w1 * w3) * (d13 * d13)) + (w2 * w3) * (d23 * d23));
+            if (D3 >= 0.0) {
+                double u3 = (((w1 * a1 + w2 * a2) + w3 * a3) + sqrt(D3)) / ((w1 + w2) + w3);
+                if (u3 > a3 && u3 < best) { best = u3; *k = 3; }
+            }
+        }
+    }
+    return best;
+}
+
 /* Batch form for tests: out[i] = G(a[3i], a[3i+1], a[3i+2], r[i]). */
 void oracle_godunov_batch(const double *a, const double *r, double *out, int64_t n)
 {
@@ -148,6 +197,7 @@ typedef struct {
 typedef struct {
     int64_t n0, n1, n2, N;
     double h;
+    const double *scale; /* per-axis spacing factors, NULL: isotropic */
     const void *F;
     int F_is_f64;
     double *T;
@@ -273,6 +323,10 @@ static double solve_quadratic(solver_t *S, int64_t p, int s)
         a[ax] = d != 0 ? best : INFINITY;
     }
     double r = S->h / F;
+    if (S->scale) {
+        int k;
+        return oracle_godunov_w(a[0], a[1], a[2], S->scale[0], S->scale[1], S->scale[2], r, &k);
+    }
     return oracle_godunov(a[0], a[1], a[2], r);
 }
 
@@ -317,11 +371,15 @@ static int update_neighbors(solver_t *S, int64_t p, int s)
 /* ------------------------------------------------------------------------ */
 int oracle_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, int F_is_f64,
                  const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, double width,
-                 double *T, uint8_t *status, int64_t *order, int64_t order_cap, oracle_stats *st_out)
+                 double *T, uint8_t *status, int64_t *order, int64_t order_cap, oracle_stats *st_out,
+                 const double *axis_scale)
 {
     if (n0 <= 0 || n1 <= 0 || n2 <= 0 || !(h > 0.0) || !isfinite(h) || !F || !T || n_seeds < 0 ||
         (n_seeds > 0 && (!seed_idx || !seed_val)) || isnan(width) || width < 0.0)
         return ORACLE_EINVAL;
+    if (axis_scale)
+        for (int ax = 0; ax < 3; ax++)
+            if (!(axis_scale[ax] > 0.0) || !isfinite(axis_scale[ax])) return ORACLE_EINVAL;
     oracle_stats st_local;
     memset(&st_local, 0, sizeof st_local);
     solver_t S;
@@ -331,6 +389,7 @@ int oracle_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, in
     S.n2 = n2;
     S.N = n0 * n1 * n2;
     S.h = h;
+    S.scale = axis_scale;
     S.F = F;
     S.F_is_f64 = F_is_f64;
     S.T = T;

@@ -4,6 +4,7 @@ exact-rational root finding, an O(N^2) scan marcher, a fast-sweeping solver,
 symmetry/scaling invariants and the paper's own two-sided construction."""
 import math
 import random
+import struct
 from fractions import Fraction
 
 import numpy as np
@@ -429,3 +430,112 @@ def test_touching_sides_match_scan_marcher(oracle_mod):
     Ts = scan_march(F, 0.125, idx, val, INF, oracle_mod.godunov)
     assert np.array_equal(T, Ts)
     assert np.any(T < 0) and np.any(T > 0)
+
+
+# --------------------------------------------------------------------------
+# Per-axis spacing (Delta x, Delta y, Delta z differ; Sec. 2.1)
+
+def exact_weighted_bracket(a, w, r, iters=90):
+    """Bisection in exact rationals for sum_i w_i max(u - a_i, 0)^2 = r^2."""
+    pairs = [(Fraction(x), Fraction(wi)) for x, wi in zip(a, w) if math.isfinite(x)]
+    fr = Fraction(r)
+    lo = min(x for x, _ in pairs)
+    hi = lo + fr * 4
+    r2 = fr * fr
+    for _ in range(iters):
+        mid = (lo + hi) / 2
+        f = sum(wi * (mid - x) ** 2 for x, wi in pairs if mid > x) - r2
+        if f < 0:
+            lo = mid
+        else:
+            hi = mid
+    return lo, hi
+
+
+def test_weighted_g_against_exact_bisection(oracle_mod):
+    rng = random.Random(13)
+    worst = 0.0
+    for i in range(1200):
+        r = rng.uniform(1e-3, 1.0)
+        base = rng.uniform(0, 20)
+        sc = [rng.uniform(0.3, 3.0) for _ in range(3)]
+        k = rng.choice([1, 2, 3, 3, 3])
+        a = [base + rng.uniform(0, 2.0 * r) for _ in range(k)] + [INF] * (3 - k)
+        perm = list(range(3))
+        rng.shuffle(perm)
+        a = [a[j] for j in perm]
+        g, _ = oracle_mod.godunov_w(a[0], a[1], a[2], sc[0], sc[1], sc[2], r)
+        w = [1.0 / (s * s) for s in sc]  # the weights as the solver forms them
+        lo, hi = exact_weighted_bracket(a, w, r)
+        fg = Fraction(g)
+        err = max(float(lo - fg), float(fg - hi), 0.0) / math.ulp(g)
+        worst = max(worst, err)
+    assert worst <= 4.0, worst
+
+
+def test_weighted_g_with_unit_scales_is_g(oracle_mod):
+    rng = random.Random(14)
+    for _ in range(3000):
+        r = rng.uniform(1e-3, 1.0)
+        a = [rng.uniform(0, 2) if rng.random() > 0.2 else INF for _ in range(3)]
+        g0 = oracle_mod.godunov(a[0], a[1], a[2], r)
+        g1, _ = oracle_mod.godunov_w(a[0], a[1], a[2], 1.0, 1.0, 1.0, r)
+        assert (g0 == g1) or (math.isinf(g0) and math.isinf(g1))
+        assert struct.pack("<d", g0) == struct.pack("<d", g1)
+
+
+def test_aniso_unit_scales_equal_isotropic_solve(oracle_mod):
+    w = inputs.random_small((11, 9, 13), n_sources=2, seed=21)
+    F, idx, val = w.numpy()
+    T0, s0, _, _ = oracle_mod.solve(F, w.h, idx, val)
+    T1, s1, _, _ = oracle_mod.solve(F, w.h, idx, val, axis_scale=(1.0, 1.0, 1.0))
+    assert np.array_equal(T0.view(np.uint64), T1.view(np.uint64)) and np.array_equal(s0, s1)
+
+
+def test_aniso_planar_front(oracle_mod):
+    """A linear T = n.x / F with |n| = 1 solves the weighted upwind equation
+    exactly: each upwind difference along axis a is n_a h s_a / F."""
+    sc = (1.0, 1.7, 0.6)
+    h, Fv = 0.05, 1.3
+    shape = (12, 10, 14)
+    n = np.array([0.3, 0.5, 0.0])
+    n[2] = math.sqrt(1.0 - n[0] ** 2 - n[1] ** 2)
+    i0, i1, i2 = np.meshgrid(*[np.arange(m) for m in shape], indexing="ij")
+    exact = (n[0] * i0 * h * sc[0] + n[1] * i1 * h * sc[1] + n[2] * i2 * h * sc[2]) / Fv
+    face = (i0 == 0) | (i1 == 0) | (i2 == 0)
+    idx = np.flatnonzero(face.reshape(-1)).astype(np.int64)
+    T, st, _, _ = oracle_mod.solve(np.full(shape, Fv), h, idx, exact.reshape(-1)[idx], axis_scale=sc)
+    assert np.max(np.abs(T - exact)) <= 1e-14 * np.max(exact)
+
+
+def test_aniso_on_axis_sums(oracle_mod):
+    """On the axes through a point source, T is the left-to-right sum of
+    h s_a / F, bit for bit (the off-axis values are larger, so never upwind)."""
+    sc = (0.7, 1.0, 2.3)
+    h, Fv, n = 0.03, 1.0, 15
+    c = n // 2
+    idx = np.array([(c * n + c) * n + c], dtype=np.int64)
+    T, _, _, _ = oracle_mod.solve(np.full((n, n, n), Fv), h, idx, np.zeros(1), axis_scale=sc)
+    for ax in range(3):
+        step = h * sc[ax] / Fv
+        acc = 0.0
+        for m in range(1, n - c):
+            acc = acc + step
+            pos = [c, c, c]
+            pos[ax] = c + m
+            assert T[tuple(pos)] == acc, (ax, m)
+
+
+def test_aniso_axis_permutation(oracle_mod):
+    """Permuting the grid axes together with their spacings permutes T, bit for
+    bit: a weight attached to the wrong axis breaks this."""
+    w = inputs.random_small((9, 12, 7), n_sources=2, seed=22)
+    F, idx, val = w.numpy()
+    sc = (0.8, 1.9, 1.3)
+    T, _, _, _ = oracle_mod.solve(F, w.h, idx, val, axis_scale=sc)
+    perm = (2, 0, 1)
+    Fp = np.ascontiguousarray(np.transpose(F, perm))
+    coords = np.unravel_index(idx, F.shape)
+    idx_p = np.ravel_multi_index(tuple(coords[a] for a in perm), Fp.shape).astype(np.int64)
+    Tp, _, _, _ = oracle_mod.solve(Fp, w.h, idx_p, val, axis_scale=tuple(sc[a] for a in perm))
+    assert np.array_equal(np.transpose(T, perm).view(np.uint64), Tp.view(np.uint64))

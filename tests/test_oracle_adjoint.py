@@ -135,3 +135,48 @@ def test_zero_outside_the_system(oracle_mod):
     # every solved point's travel time decreases when its speed grows
     acc = (st & 3) == 2
     assert np.all(g[acc] < 0.0)
+
+
+def test_line_closed_form_with_spacing(oracle_mod):
+    """The 1-D closed form on a line along axis 1 with spacing h s: dL/dF_j =
+    -(h s / F_j^2) sum_{i>=j} c_i."""
+    rng = np.random.default_rng(9)
+    n, h, s = 17, 0.05, 2.5
+    F = rng.uniform(0.5, 2.0, size=(1, n, 1))
+    sc = (0.7, s, 1.3)
+    T, st, _, _ = oracle_mod.solve(F, h, np.array([0], dtype=np.int64), np.zeros(1), axis_scale=sc)
+    c = rng.normal(size=(1, n, 1))
+    g = oadj.dense_adjoint(F, h, T, st, c, axis_scale=sc)
+    f = F.reshape(-1)
+    expect = -(h * s / f ** 2) * np.cumsum(c.reshape(-1)[::-1])[::-1]
+    expect[0] = 0.0
+    np.testing.assert_allclose(g.reshape(-1), expect, rtol=1e-13, atol=1e-15)
+
+
+def test_finite_differences_with_spacing(oracle_mod):
+    w = inputs.random_small((9, 10, 11), n_sources=2, seed=5)
+    F, idx, val = w.numpy()
+    sc = (0.6, 1.4, 1.0)
+    T, st, _, _ = oracle_mod.solve(F, w.h, idx, val, axis_scale=sc)
+    rng = np.random.default_rng(55)
+    rec = rng.choice(T.size, size=30, replace=False)
+    d = T.reshape(-1)[rec] * (1.0 + 0.05 * rng.normal(size=30))
+    _, dL = loss_and_grad(T, rec, d)
+    g = oadj.dense_adjoint(F, w.h, T, st, dL, axis_scale=sc)
+    gm = np.abs(g.reshape(-1))
+    cells = rng.choice(np.flatnonzero(gm > 1e-3 * gm.max()), size=16, replace=False)
+    used = 0
+    for c in cells:
+        vals = []
+        for s_ in (-1.0, 0.0, 1.0):
+            Fp = F.copy()
+            Fp.reshape(-1)[c] += s_ * 1e-6
+            Tp, _, _, _ = oracle_mod.solve(Fp, w.h, idx, val, axis_scale=sc)
+            vals.append(loss_and_grad(Tp, rec, d)[0])
+        lo, mid, hi = vals
+        if abs((hi - mid) - (mid - lo)) > 1e-4 * abs(hi - lo) / 2:
+            continue
+        used += 1
+        central = (hi - lo) / 2e-6
+        assert abs(g.reshape(-1)[c] - central) <= 1e-6 * abs(central), c
+    assert used >= 12
