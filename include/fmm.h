@@ -93,6 +93,11 @@ typedef struct {
      * precedence over `stride` (useful for a batch whose problems have
      * different spacings). */
     double stride_h;
+    /* Per-axis grid spacing factors: the spacing along axis a is
+     * h * axis_scale[a] (the paper's Delta x, Delta y, Delta z, Sec. 2.1).
+     * 0 means 1; all 1 is the uniform grid.  The local solver then solves
+     * sum_a max(u - a_a, 0)^2 / axis_scale[a]^2 = (h / F)^2. */
+    double axis_scale[3];
 } fmm_opts;
 
 typedef struct {
@@ -114,7 +119,7 @@ typedef struct {
 
 /* Fill *opts with the defaults: band_width = INFINITY, stride = 2h (<= 0),
  * tile_edge = 8, max_restarts = 0, flags = 0, time_limit_s = 0 (300 s),
- * stride_h = 0 (unused). */
+ * stride_h = 0 (unused), axis_scale = {0, 0, 0} (uniform grid). */
 void fmm_default_opts(fmm_opts *opts);
 
 /* Bytes of device workspace fmm_solve() needs for this problem (0 if the
@@ -258,6 +263,7 @@ typedef struct {
     const uint8_t *status;
     const double *dL_dT;
     double *dL_dF;
+    double axis_scale[3]; /* the forward solve's fmm_opts.axis_scale (0 means 1) */
 } fmm_adjoint_problem;
 
 typedef struct {
@@ -277,7 +283,8 @@ size_t fmm_adjoint_workspace_bytes(int64_t n_problems, const fmm_adjoint_problem
 int fmm_adjoint_batch(int64_t n_problems, const fmm_adjoint_problem *problems, fmm_dtype F_dtype,
                       void *workspace, size_t workspace_bytes, void *stream);
 
-/* Single-problem form of fmm_adjoint_batch(). */
+/* Single-problem form of fmm_adjoint_batch() on a uniform grid (use the
+ * batch form for per-axis spacing). */
 int fmm_adjoint(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_dtype F_dtype, const double *T,
                 const uint8_t *status, const double *dL_dT, double *dL_dF, void *workspace, size_t workspace_bytes,
                 void *stream);

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "fmm_device.h"
+
 namespace fmm {
 
 // One problem of an adjoint batch (device copy).  Arrays are the caller's,
@@ -19,6 +21,7 @@ struct AdjInst {
     const uint8_t *status;
     const double *dL_dT;
     double *dL_dF;
+    Spacing sp;  // per-axis spacing factors (weights 1 / s^2)
 };
 
 enum : uint32_t { ADJ_ERR_BARRIER = 32u };

@@ -6,13 +6,14 @@
 // with F_p > 0 satisfies, with u = |T| and U_p its upwind set (for each of the
 // k axes whose values the local solver's root used, the neighbour on that
 // axis with the smaller value),
-//     sum_{q in U_p} (u_p - u_q)^2 = (h / F_p)^2,
+//     sum_{q in U_p} w_q (u_p - u_q)^2 = (h / F_p)^2,
+// (w_q = 1 / s^2 for a grid spacing h s along q's axis, 1 on a uniform grid)
 // and its linearisation is
-//     S_p du_p - sum_{q in U_p} (u_p - u_q) du_q = -(h^2 / F_p^3) dF_p,
-//     S_p = sum_{q in U_p} (u_p - u_q).
+//     S_p du_p - sum_{q in U_p} w_q (u_p - u_q) du_q = -(h^2 / F_p^3) dF_p,
+//     S_p = sum_{q in U_p} w_q (u_p - u_q).
 // Seeds and points outside the accepted set are fixed.  The transposed system
 // is solved exactly, in reverse dependency order: with lt_q = S_q lambda_q,
-//     lt_q = dL/du_q + sum_{p : q in U_p} ((u_p - u_q) / S_p) lt_p,
+//     lt_q = dL/du_q + sum_{p : q in U_p} (w_q (u_p - u_q) / S_p) lt_p,
 //     dL/dF_p = -(h^2 / (F_p^3 S_p)) lt_p,
 // where dL/du = sign(T) dL/dT.  Since u_q < u_p for q in U_p, the dependency
 // graph is acyclic: a point is final once all the points that used it are.
@@ -74,7 +75,7 @@ __device__ __forceinline__ uint32_t upwind_code(const AdjInst &I, int64_t p, int
         }
     }
     int k = 0;
-    (void)godunov_sel(a[0], a[1], a[2], I.h / f, &k);
+    (void)local_solve(I.sp, a[0], a[1], a[2], I.h / f, &k);
     // the k smallest per-axis values, ties in axis order
     uint32_t code = 0;
 #pragma unroll
@@ -186,9 +187,11 @@ __device__ __forceinline__ void adj_point(const AdjParams &P, uint64_t it, bool 
     double S = 0.0;
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
+        // weighted difference w_a (u_p - u_q), w_a = 1 / s_a^2 (1 on a uniform grid)
         const uint32_t cc = (code >> (2 * ax)) & 3u;
+        const double w = I.sp.aniso ? 1.0 / (I.sp.s[ax] * I.sp.s[ax]) : 1.0;
         q[ax] = cc == 0 ? -1 : (cc == 1 ? p - str[ax] : p + str[ax]);
-        d[ax] = cc == 0 ? 0.0 : up - fabs(I.T[q[ax]]);
+        d[ax] = cc == 0 ? 0.0 : w * (up - fabs(I.T[q[ax]]));
         S += d[ax];
     }
     // this point's gradient term; its accumulator is not needed any more

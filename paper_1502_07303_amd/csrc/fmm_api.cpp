@@ -30,7 +30,21 @@ bool opts_ok(const fmm_opts *o)
     if (!(o->tile_edge == 0 || o->tile_edge == 4 || o->tile_edge == 8 || o->tile_edge == 16)) return false;
     if (o->max_restarts < 0) return false;
     if (o->flags & ~(uint32_t)(FMM_VALIDATE | FMM_TIMING | FMM_ONE_MARCH)) return false;
+    for (int a = 0; a < 3; a++)
+        if (!(o->axis_scale[a] == 0.0 || (o->axis_scale[a] > 0.0 && isfinite(o->axis_scale[a])))) return false;
     return true;
+}
+
+// Effective spacing factors: 0 means 1; the weighted solver only when one differs.
+Spacing spacing_of(const double sc[3])
+{
+    Spacing sp;
+    sp.aniso = 0;
+    for (int a = 0; a < 3; a++) {
+        sp.s[a] = sc[a] == 0.0 ? 1.0 : sc[a];
+        if (sp.s[a] != 1.0) sp.aniso = 1;
+    }
+    return sp;
 }
 
 bool problem_ok(const fmm_problem &q)
@@ -68,6 +82,7 @@ Params make_params(const Layout &L, void *ws, const fmm_opts &o)
     char *b = (char *)ws;
     Params P;
     memset(&P, 0, sizeof P);
+    P.sp = spacing_of(o.axis_scale);
     P.n_inst = L.n_inst;
     P.ntiles = L.ntiles;
     P.mask_words = L.mask_words;
@@ -395,6 +410,8 @@ static bool adj_problem_ok(const fmm_adjoint_problem &q)
     uint64_t nt;
     if (!tile_grid(q.n0, q.n1, q.n2, 4, t, &nt)) return false;
     if (!(q.h > 0.0) || !isfinite(q.h)) return false;
+    for (int a = 0; a < 3; a++)
+        if (!(q.axis_scale[a] == 0.0 || (q.axis_scale[a] > 0.0 && isfinite(q.axis_scale[a])))) return false;
     return q.F && q.T && q.status && q.dL_dT && q.dL_dF;
 }
 
@@ -415,6 +432,7 @@ static uint64_t adj_total(int64_t n, const fmm_adjoint_problem *q, std::vector<A
             I.status = q[i].status;
             I.dL_dT = q[i].dL_dT;
             I.dL_dF = q[i].dL_dF;
+            I.sp = spacing_of(q[i].axis_scale);
         }
         total += (uint64_t)(q[i].n0 * q[i].n1 * q[i].n2);
     }
@@ -480,6 +498,7 @@ int fmm_adjoint(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm
     q.status = status;
     q.dL_dT = dL_dT;
     q.dL_dF = dL_dF;
+    q.axis_scale[0] = q.axis_scale[1] = q.axis_scale[2] = 0.0;
     return fmm_adjoint_batch(1, &q, F_dtype, workspace, workspace_bytes, stream);
 }
 

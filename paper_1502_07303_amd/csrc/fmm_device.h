@@ -61,6 +61,68 @@ __device__ __forceinline__ double godunov(double x, double y, double z, double r
     return godunov_sel(x, y, z, r, &k);
 }
 
+// The local solver with per-axis spacing h s_i (weights w_i = 1 / s_i^2):
+// sum_i w_i max(u - a_i, 0)^2 = r^2, r = h / F.  For the k smallest values,
+// sorted together with their scales (ties keep axis order),
+//   u1 = a1 + r s1
+//   u2 = ((w1 a1 + w2 a2) + sqrt((w1+w2) r^2 - (w1 w2)(a2-a1)^2)) / (w1+w2)
+//   u3 = (((w1 a1 + w2 a2) + w3 a3) + sqrt(((w1+w2)+w3) r^2
+//          - (((w1 w2)(a2-a1)^2 + (w1 w3)(a3-a1)^2) + (w2 w3)(a3-a2)^2))) / ((w1+w2)+w3)
+// with the same causality rule and minimum.  With unit scales every
+// operation is the one of godunov_sel().
+__device__ __forceinline__ double godunov_w_sel(double x, double y, double z, double sx, double sy, double sz,
+                                                double r, int *k)
+{
+    double a1 = x, a2 = y, a3 = z, s1 = sx, s2 = sy, s3 = sz, t;
+    if (a1 > a2) { t = a1; a1 = a2; a2 = t; t = s1; s1 = s2; s2 = t; }
+    if (a2 > a3) {
+        t = a2; a2 = a3; a3 = t; t = s2; s2 = s3; s3 = t;
+        if (a1 > a2) { t = a1; a1 = a2; a2 = t; t = s1; s1 = s2; s2 = t; }
+    }
+    const double w1 = 1.0 / (s1 * s1), w2 = 1.0 / (s2 * s2), w3 = 1.0 / (s3 * s3);
+    *k = 0;
+    if (!(a1 < FMM_INF)) return FMM_INF;
+    double r2 = r * r;
+    double best = a1 + r * s1;
+    *k = 1;
+    if (a2 < FMM_INF) {
+        double d12 = a2 - a1;
+        double D2 = (w1 + w2) * r2 - (w1 * w2) * (d12 * d12);
+        if (D2 >= 0.0) {
+            double u2 = ((w1 * a1 + w2 * a2) + sqrt(D2)) / (w1 + w2);
+            if (u2 > a2 && u2 < best) {
+                best = u2;
+                *k = 2;
+            }
+        }
+        if (a3 < FMM_INF) {
+            double d13 = a3 - a1, d23 = a3 - a2;
+            double D3 = ((w1 + w2) + w3) * r2 -
+                        (((w1 * w2) * (d12 * d12) + (w1 * w3) * (d13 * d13)) + (w2 * w3) * (d23 * d23));
+            if (D3 >= 0.0) {
+                double u3 = (((w1 * a1 + w2 * a2) + w3 * a3) + sqrt(D3)) / ((w1 + w2) + w3);
+                if (u3 > a3 && u3 < best) {
+                    best = u3;
+                    *k = 3;
+                }
+            }
+        }
+    }
+    return best;
+}
+
+// Per-axis grid spacing factors of a solve (spacing h * s[a] along axis a).
+struct Spacing {
+    double s[3];
+    int aniso;  // 0: all factors are 1 (the isotropic solver is used)
+};
+
+__device__ __forceinline__ double local_solve(const Spacing &sp, double x, double y, double z, double r, int *k)
+{
+    if (sp.aniso) return godunov_w_sel(x, y, z, sp.s[0], sp.s[1], sp.s[2], r, k);
+    return godunov_sel(x, y, z, r, k);
+}
+
 // ---------------------------------------------------------------------------
 // Small helpers.
 

@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "fmm_device.h"
+
 namespace fmm {
 
 // Per-restart bookkeeping of the shared tile lists.  Restart r reads
@@ -188,6 +190,7 @@ inline bool make_layout(int64_t n_inst, const int64_t *dims, int E, size_t fsize
 }
 
 struct Params {
+    Spacing sp;  // per-axis spacing factors of the batch
     uint32_t n_inst;
     uint32_t ntiles;  // over all problems
     uint32_t mask_words;

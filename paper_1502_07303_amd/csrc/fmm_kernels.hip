@@ -255,7 +255,8 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 // magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z) and which of them
 // are updatable interior cells.
 template <int E, typename FT>
-__device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, double h, const double bnd[2], double &out,
+__device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
+                                           const double bnd[2], double &out,
                                            double &vp, double na[6], uint32_t &upd)
 {
     using G = Geo<E>;
@@ -298,7 +299,8 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, int p, doubl
         const double y = side == 0 ? am[1] : ap3[1];
         const double z = side == 0 ? am[2] : ap3[2];
         if (!(fmin(x, fmin(y, z)) < FMM_INF)) continue;
-        const double u = godunov(x, y, z, r);
+        int kk;
+        const double u = local_solve(sp, x, y, z, r, &kk);
         const bool take = u < best || (side == 0 && u == best && !neg && best < FMM_INF);
         if (take) {
             best = u;
@@ -338,7 +340,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             int p = 0;
             if (k < n) {
                 p = L.list[k];
-                ch = eval_point(L, p, h, th, nv, vp, na, upd);
+                ch = eval_point(L, P.sp, p, h, th, nv, vp, na, upd);
                 ws.n_solve++;
             }
             wave_sync();
@@ -646,9 +648,15 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     // source value is sent at once (the neighbour re-marches, KNOWN_OLD of Alg.
     // 15), a band value only joins the neighbour's pending minimum (BAND_OLD).
     uint32_t fsrc = 0, fany = 0;
+#ifdef FMM_PROFILE
+    bool any_chg = false;
+#endif
     for (int p = lane; p < V; p += 64) {
         const int d = G::domp(p);
         const bool chg = (L.fl[d] & FL_CHG) != 0;
+#ifdef FMM_PROFILE
+        any_chg |= chg;
+#endif
         if (!(chg || fresh)) continue;
         const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
         const double v = L.T[d];
@@ -669,6 +677,9 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 if ((fm >> f) & 1u) atomicMin(&L.bm[f * 2 + sd], b);
         }
     }
+#ifdef FMM_PROFILE
+    PROF_ADD(15, (__ballot(any_chg) == 0ull && mode == MODE_M2) ? 1 : 0);
+#endif
     uint32_t srcFaces = 0, anyFaces = 0;
 #pragma unroll
     for (int f = 0; f < 6; f++) {

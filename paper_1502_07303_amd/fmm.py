@@ -32,7 +32,8 @@ ST_FAR, ST_BAND, ST_ACCEPTED, ST_SEED, ST_NEG = 0, 1, 2, 3, 0x80
 class FmmOpts(ctypes.Structure):
     _fields_ = [("band_width", ctypes.c_double), ("stride", ctypes.c_double),
                 ("inner_stride", ctypes.c_double), ("tile_edge", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("time_limit_s", ctypes.c_uint32), ("stride_h", ctypes.c_double)]
+                ("flags", ctypes.c_uint32), ("time_limit_s", ctypes.c_uint32), ("stride_h", ctypes.c_double),
+                ("axis_scale", ctypes.c_double * 3)]
 
 
 class FmmStats(ctypes.Structure):
@@ -57,7 +58,7 @@ class FmmProblem(ctypes.Structure):
 class FmmAdjointProblem(ctypes.Structure):
     _fields_ = [("n0", ctypes.c_int64), ("n1", ctypes.c_int64), ("n2", ctypes.c_int64), ("h", ctypes.c_double),
                 ("F", ctypes.c_void_p), ("T", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("dL_dT", ctypes.c_void_p), ("dL_dF", ctypes.c_void_p)]
+                ("dL_dT", ctypes.c_void_p), ("dL_dF", ctypes.c_void_p), ("axis_scale", ctypes.c_double * 3)]
 
 
 class FmmAdjointStats(ctypes.Structure):
@@ -125,7 +126,8 @@ def strerror(code: int) -> str:
 
 
 def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, validate=False,
-              time_limit_s=0, timing=False, inner_stride=None, one_march=False, stride_h=None) -> FmmOpts:
+              time_limit_s=0, timing=False, inner_stride=None, one_march=False, stride_h=None,
+              axis_scale=None) -> FmmOpts:
     o = FmmOpts()
     load_library().fmm_default_opts(ctypes.byref(o))
     o.band_width = float(band_width)
@@ -136,6 +138,9 @@ def make_opts(band_width=math.inf, stride=None, tile_edge=0, max_restarts=0, val
     o.flags = (FMM_VALIDATE if validate else 0) | (FMM_TIMING if timing else 0) | (FMM_ONE_MARCH if one_march else 0)
     o.time_limit_s = int(time_limit_s)
     o.stride_h = 0.0 if stride_h is None else float(stride_h)
+    if axis_scale is not None:
+        for a in range(3):
+            o.axis_scale[a] = float(axis_scale[a])
     return o
 
 
@@ -160,12 +165,12 @@ class Solver:
 
     def __init__(self, shape, n_seeds, h, band_width=math.inf, stride=None, tile_edge=0, max_restarts=0,
                  validate=False, device="cuda", time_limit_s=0, timing=False, inner_stride=None,
-                 speed_dtype=torch.float64, one_march=False):
+                 speed_dtype=torch.float64, one_march=False, axis_scale=None):
         self.lib = load_library()
         self.shape = tuple(int(x) for x in shape)
         self.h = float(h)
         self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s, timing,
-                              inner_stride, one_march)
+                              inner_stride, one_march, axis_scale=axis_scale)
         if speed_dtype not in (torch.float32, torch.float64):
             raise FmmError(FMM_EINVAL, f"unsupported speed dtype {speed_dtype}")
         self.speed_dtype = speed_dtype
@@ -220,10 +225,11 @@ class Solver:
 
 def solve(F: torch.Tensor, h: float, seed_idx: torch.Tensor, seed_val: torch.Tensor, band_width=math.inf,
           stride=None, tile_edge=0, max_restarts=0, validate=False, with_status=True, check=True,
-          time_limit_s=0, inner_stride=None, one_march=False):
+          time_limit_s=0, inner_stride=None, one_march=False, axis_scale=None):
     """One solve on F's device; returns (T, status, stats) after synchronising."""
     s = Solver(F.shape, seed_idx.numel(), h, band_width, stride, tile_edge, max_restarts, validate, F.device,
-               time_limit_s, inner_stride=inner_stride, speed_dtype=F.dtype, one_march=one_march)
+               time_limit_s, inner_stride=inner_stride, speed_dtype=F.dtype, one_march=one_march,
+               axis_scale=axis_scale)
     T = torch.empty(F.shape, dtype=torch.float64, device=F.device)
     status = torch.empty(F.shape, dtype=torch.uint8, device=F.device) if with_status else None
     s.solve_into(F, seed_idx, seed_val, T, status)
@@ -266,7 +272,7 @@ class BatchSolver:
 
     def __init__(self, problems, band_width=math.inf, stride=None, stride_h=None, tile_edge=0, max_restarts=0,
                  validate=False, time_limit_s=0, timing=False, inner_stride=None, one_march=False,
-                 with_status=True, workspace_edges=None, T_out=None, status_out=None):
+                 with_status=True, workspace_edges=None, T_out=None, status_out=None, axis_scale=None):
         self.lib = load_library()
         if not problems:
             raise FmmError(FMM_EINVAL, "empty batch")
@@ -312,12 +318,12 @@ class BatchSolver:
         self.n = n
         self.problems = arr
         self.opts = make_opts(band_width, stride, tile_edge, max_restarts, validate, time_limit_s, timing,
-                              inner_stride, one_march, stride_h)
+                              inner_stride, one_march, stride_h, axis_scale)
         edges = workspace_edges or [self.opts.tile_edge or 8]
         nbytes = 0
         for e in edges:
             o = make_opts(band_width, stride, e, max_restarts, validate, time_limit_s, timing, inner_stride,
-                          one_march, stride_h)
+                          one_march, stride_h, axis_scale)
             b = int(self.lib.fmm_batch_workspace_bytes(n, arr, self.dtype, ctypes.byref(o)))
             if b == 0:
                 raise FmmError(FMM_EINVAL, "invalid batch or options")
@@ -397,6 +403,10 @@ class AdjointSolver:
             p.h = float(q["h"])
             p.F, p.T, p.status = F.data_ptr(), T.data_ptr(), st.data_ptr()
             p.dL_dT, p.dL_dF = gT.data_ptr(), gF.data_ptr()
+            sc = q.get("axis_scale")
+            if sc is not None:
+                for a in range(3):
+                    p.axis_scale[a] = float(sc[a])
         self.n = n
         self.problems = arr
         nbytes = int(self.lib.fmm_adjoint_workspace_bytes(n, arr))
@@ -422,10 +432,11 @@ class AdjointSolver:
         return st
 
 
-def adjoint(F, h, T, status, dL_dT):
+def adjoint(F, h, T, status, dL_dT, axis_scale=None):
     """dL/dF (float64, F's shape) for one solved problem."""
     gF = torch.empty(F.shape, dtype=torch.float64, device=F.device)
-    a = AdjointSolver([{"F": F, "h": h, "T": T, "status": status, "dL_dT": dL_dT.contiguous(), "dL_dF": gF}])
+    a = AdjointSolver([{"F": F, "h": h, "T": T, "status": status, "dL_dT": dL_dT.contiguous(), "dL_dF": gF,
+                        "axis_scale": axis_scale}])
     a.run()
     a.stats()
     return gF
@@ -434,22 +445,24 @@ def adjoint(F, h, T, status, dL_dT):
 class Eikonal(torch.autograd.Function):
     """T = solve(F) with the library's adjoint as backward: dL/dF from dL/dT.
 
-    ``forward(F, h, seed_idx, seed_val, band_width=inf, stride=None)`` returns
-    (T, status); status is not differentiable."""
+    ``forward(F, h, seed_idx, seed_val, band_width=inf, stride=None,
+    axis_scale=None)`` returns (T, status); status is not differentiable."""
 
     @staticmethod
-    def forward(ctx, F, h, seed_idx, seed_val, band_width=math.inf, stride=None):
-        T, st, _ = solve(F.detach().contiguous(), h, seed_idx, seed_val, band_width=band_width, stride=stride)
+    def forward(ctx, F, h, seed_idx, seed_val, band_width=math.inf, stride=None, axis_scale=None):
+        T, st, _ = solve(F.detach().contiguous(), h, seed_idx, seed_val, band_width=band_width, stride=stride,
+                         axis_scale=axis_scale)
         ctx.save_for_backward(F, T, st)
         ctx.h = float(h)
+        ctx.axis_scale = axis_scale
         ctx.mark_non_differentiable(st)
         return T, st
 
     @staticmethod
     def backward(ctx, gT, gst):
         F, T, st = ctx.saved_tensors
-        g = adjoint(F.detach().contiguous(), ctx.h, T, st, gT.to(torch.float64).contiguous())
-        return g.to(F.dtype), None, None, None, None, None
+        g = adjoint(F.detach().contiguous(), ctx.h, T, st, gT.to(torch.float64).contiguous(), ctx.axis_scale)
+        return g.to(F.dtype), None, None, None, None, None, None
 
 
 class EikonalShots(torch.autograd.Function):
@@ -472,6 +485,7 @@ class EikonalShots(torch.autograd.Function):
         b.stats()
         ctx.save_for_backward(Fd, T, st)
         ctx.h = float(h)
+        ctx.axis_scale = (opts or {}).get("axis_scale")
         ctx.mark_non_differentiable(st)
         return T, st
 
@@ -480,8 +494,8 @@ class EikonalShots(torch.autograd.Function):
         F, T, st = ctx.saved_tensors
         gT = gT.to(torch.float64).contiguous()
         gF = torch.empty(F.shape, dtype=torch.float64, device=F.device)
-        a = AdjointSolver([{"F": F, "h": ctx.h, "T": T[k], "status": st[k], "dL_dT": gT[k], "dL_dF": gF}
-                           for k in range(T.shape[0])])
+        a = AdjointSolver([{"F": F, "h": ctx.h, "T": T[k], "status": st[k], "dL_dT": gT[k], "dL_dF": gF,
+                            "axis_scale": ctx.axis_scale} for k in range(T.shape[0])])
         a.run()
         a.stats()
         return gF.to(F.dtype), None, None, None

@@ -105,11 +105,16 @@ def test_host_rejects_bad_arguments(fmm, kw):
 
 
 @pytest.mark.parametrize("opt", [dict(band_width=-1.0), dict(band_width=math.nan), dict(stride=math.nan),
-                                 dict(tile_edge=6), dict(max_restarts=-2)])
+                                 dict(tile_edge=6), dict(max_restarts=-2), dict(axis_scale=(1.0, -2.0, 1.0)),
+                                 dict(axis_scale=(math.nan, 1.0, 1.0)), dict(axis_scale=(1.0, 1.0, math.inf))])
 def test_host_rejects_bad_options(fmm, opt):
     o = fmm.make_opts()
     for k, v in opt.items():
-        setattr(o, k, v)
+        if k == "axis_scale":
+            for a in range(3):
+                o.axis_scale[a] = v[a]
+        else:
+            setattr(o, k, v)
     assert _call(fmm, opts=o) == fmm.FMM_EINVAL
 
 
