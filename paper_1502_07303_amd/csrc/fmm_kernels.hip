@@ -254,7 +254,7 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 // the update step needs without another LDS round trip: the old value, the
 // magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z) and which of them
 // are updatable interior cells.
-template <int E, typename FT>
+template <int E, typename FT, bool AN>
 __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
                                            const double bnd[2], double &out,
                                            double &vp, double na[6], uint32_t &upd)
@@ -300,7 +300,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
         const double z = side == 0 ? am[2] : ap3[2];
         if (!(fmin(x, fmin(y, z)) < FMM_INF)) continue;
         int kk;
-        const double u = local_solve(sp, x, y, z, r, &kk);
+        const double u = AN ? godunov_w_sel(x, y, z, sp.s[0], sp.s[1], sp.s[2], r, &kk) : godunov_sel(x, y, z, r, &kk);
         const bool take = u < best || (side == 0 && u == best && !neg && best < FMM_INF);
         if (take) {
             best = u;
@@ -319,7 +319,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
 // Neighbours are marked from the magnitudes the evaluation read; values only
 // decrease, so a neighbour lowered meanwhile is at worst marked needlessly,
 // never missed.
-template <int E, typename FT>
+template <int E, typename FT, bool AN>
 __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double h, const double th[2], const double lastb[2],
                                      WaveState &ws)
 {
@@ -340,7 +340,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             int p = 0;
             if (k < n) {
                 p = L.list[k];
-                ch = eval_point(L, P.sp, p, h, th, nv, vp, na, upd);
+                ch = eval_point<E, FT, AN>(L, P.sp, p, h, th, nv, vp, na, upd);
                 ws.n_solve++;
             }
             wave_sync();
@@ -459,7 +459,7 @@ struct TileGeo {
 // earlier phase (visit stamp); otherwise its cells count as +inf, which is a
 // valid upper bound, and the writer's flag makes this tile read them again.
 
-template <int E, typename FT>
+template <int E, typename FT, bool AN>
 __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, const TileGeo &G0, uint32_t t, int mode,
                                            uint32_t dbits,
                                            const double bnd[2], const double lastb[2], uint32_t epoch, uint32_t phase,
@@ -622,7 +622,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     PROF_ADD(3, t_marked - t_loaded);
     for (;;) {
         PROF_CLOCK(t_r0);
-        rounds += relax(P, L, G0.h, th, lastb, ws);
+        rounds += relax<E, FT, AN>(P, L, G0.h, th, lastb, ws);
         PROF_CLOCK(t_r1);
         PROF_ADD(4, t_r1 - t_r0);
         PROF_ADD(8, 1);
@@ -820,7 +820,7 @@ __device__ __forceinline__ void flush_acc(const Params &P, WaveState &ws, uint32
     ws.gmin0 = ws.gmin1 = FMM_INF;
 }
 
-template <int E, int NW, typename FT>
+template <int E, int NW, typename FT, bool AN>
 __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
                                           uint32_t phase, const uint32_t *items, uint32_t nitems, WaveState &ws)
 {
@@ -917,7 +917,7 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             }
             wave_sync();
         }
-        tile_march<E, FT>(P, L, iv.g, t, mode, dbits, iv.bnd, lastb, epoch, phase, second, ws, listNext,
+        tile_march<E, FT, AN>(P, L, iv.g, t, mode, dbits, iv.bnd, lastb, epoch, phase, second, ws, listNext,
                           &nxt.live_len, P.dlist, &cur.d_len, dprod);
     }
 
@@ -975,7 +975,7 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
     ws.gmin0 = ws.gmin1 = FMM_INF;
 }
 
-template <int E, int NW, typename FT>
+template <int E, int NW, typename FT, bool AN>
 __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
 {
     __shared__ WaveLds<E, FT> s_wave[NW];
@@ -1011,7 +1011,7 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
     bool run = ld_acq(&c->error) == 0;
     while (run) {
         PROF_CLOCK(t_p0);
-        run_phase<E, NW, FT>(P, L, s_g, mode, r, phase, items, nitems, ws);
+        run_phase<E, NW, FT, AN>(P, L, s_g, mode, r, phase, items, nitems, ws);
         PROF_CLOCK(t_p1);
         const bool passed = grid_barrier(c, gen, nwg, &s_g.ok);
         PROF_CLOCK(t_p2);
@@ -1448,10 +1448,11 @@ hipError_t launch_prepare(const Params &P, const Inst *insts, int64_t n, int E, 
     }
 }
 
-template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_out)
+template <int E, int NW, typename FT, bool AN>
+static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_out)
 {
     static int occ = -1;
-    auto kern = k_driver<E, NW, FT>;
+    auto kern = k_driver<E, NW, FT, AN>;
     if (occ < 0) {
         int nb = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NW * 64, 0);
@@ -1477,16 +1478,27 @@ template <int E, int NW, typename FT> static hipError_t launch_driver_t(const Pa
     return hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(NW * 64), args, 0, s);
 }
 
-hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
+// The weighted local solver (per-axis spacing) is a separate instantiation,
+// so the uniform-grid march carries none of its code.
+template <bool AN> static hipError_t launch_driver_a(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
 {
     switch (E) {
-    case 4: return f64 ? launch_driver_t<4, 12, double>(P, s, nwg_out) : launch_driver_t<4, 12, float>(P, s, nwg_out);
+    case 4:
+        return f64 ? launch_driver_t<4, 12, double, AN>(P, s, nwg_out)
+                   : launch_driver_t<4, 12, float, AN>(P, s, nwg_out);
     case 8:
-        return f64 ? launch_driver_t<8, FMM_E8_WAVES_F64, double>(P, s, nwg_out)
-                   : launch_driver_t<8, FMM_E8_WAVES_F32, float>(P, s, nwg_out);
-    case 16: return f64 ? launch_driver_t<16, 1, double>(P, s, nwg_out) : launch_driver_t<16, 1, float>(P, s, nwg_out);
+        return f64 ? launch_driver_t<8, FMM_E8_WAVES_F64, double, AN>(P, s, nwg_out)
+                   : launch_driver_t<8, FMM_E8_WAVES_F32, float, AN>(P, s, nwg_out);
+    case 16:
+        return f64 ? launch_driver_t<16, 1, double, AN>(P, s, nwg_out)
+                   : launch_driver_t<16, 1, float, AN>(P, s, nwg_out);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
+{
+    return P.sp.aniso ? launch_driver_a<true>(P, E, f64, s, nwg_out) : launch_driver_a<false>(P, E, f64, s, nwg_out);
 }
 
 template <int E> static hipError_t launch_finalize_t(const Params &P, const Inst *insts, int64_t n, hipStream_t s)
