@@ -39,7 +39,8 @@ def log(*a):
 def read_traffic(kernel_tag, stride_h):
     """HBM bytes per driver launch from the committed rocprofv3 counter summary,
     if it was taken with the current kernel build (tag match) at the same
-    restart stride; else None."""
+    restart stride (lines "hbm_bytes_per_launch_stride_<s>h: <bytes>"); else
+    None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -51,12 +52,7 @@ def read_traffic(kernel_tag, stride_h):
     if vals.get("kernel_tag") != kernel_tag:
         return None
     try:
-        if float(vals.get("stride_h", "nan")) != float(stride_h):
-            return None
-    except ValueError:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[f"hbm_bytes_per_launch_stride_{float(stride_h):g}h"])
     except (KeyError, ValueError):
         return None
 
@@ -64,7 +60,7 @@ def read_traffic(kernel_tag, stride_h):
 def kernel_tag():
     import hashlib
     h = hashlib.sha256()
-    for f in ("fmm_kernels.hip", "fmm_internal.h", "fmm_api.cpp"):
+    for f in ("fmm_kernels.hip", "fmm_internal.h", "fmm_device.h", "fmm_api.cpp"):
         with open(os.path.join(ROOT, "paper_1502_07303_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -229,7 +225,7 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--stride-h", type=float, default=None,
                     help="restart stride in units of h (inf allowed); default: swept by the library's autotuner")
-    ap.add_argument("--sweep", default="2,3,4,5", help="strides (units of h) the autotuner tries")
+    ap.add_argument("--sweep", default="3,4,5", help="strides (units of h) the autotuner tries")
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-crop", type=int, default=352)
