@@ -153,7 +153,8 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
 
 /* Synchronise `stream`, copy the statistics of the last solve that used
  * `workspace` into *out (host), and return FMM_OK, or FMM_ENOCONV /
- * FMM_EDEVICE when the device recorded an error.  The stage timings of
+ * FMM_EDEVICE when the device recorded an error (FMM_EINVAL for a workspace
+ * no solve has used).  The stage timings of
  * FMM_TIMING belong to the last timed solve on this workspace; the events
  * are host-side objects the library keeps per workspace address. */
 int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream);

@@ -25,6 +25,7 @@ struct AdjInst {
 };
 
 enum : uint32_t { ADJ_ERR_BARRIER = 32u };
+constexpr uint32_t ADJ_MAGIC = 0x41444a31u;
 
 struct AdjCtrl {
     alignas(128) uint32_t bar;  // grid barrier arrivals (monotonic)
@@ -33,6 +34,7 @@ struct AdjCtrl {
     uint32_t n_inst;
     uint32_t nwg;
     uint32_t levels;                  // frontier levels processed
+    uint32_t magic;                   // ADJ_MAGIC once a run has initialised the workspace
     alignas(128) unsigned long long len[3];  // frontier lengths, by level mod 3
     alignas(128) unsigned long long n_points;  // points of the linear system
 };

@@ -271,6 +271,7 @@ __global__ void k_adj_init(AdjParams P, uint32_t n_inst)
         c->levels = 0;
         c->len[0] = c->len[1] = c->len[2] = 0;
         c->n_points = 0;
+        c->magic = ADJ_MAGIC;
     }
 }
 

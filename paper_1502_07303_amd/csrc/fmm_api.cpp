@@ -216,7 +216,9 @@ int read_stats(const void *workspace, int64_t n, fmm_stats *out, void *stream)
     Ctrl c;
     if (hipMemcpyAsync(&c, workspace, sizeof c, hipMemcpyDeviceToHost, s) != hipSuccess) return FMM_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return FMM_EHIP;
-    if (c.n_inst == 0 || (int64_t)c.n_inst < n) return FMM_EINVAL;
+    // a workspace no solve has initialised holds no statistics
+    if (c.magic != CTRL_MAGIC || c.n_inst == 0 || c.n_inst > MAX_PROBLEMS || (int64_t)c.n_inst < n)
+        return FMM_EINVAL;
     // the per-problem records follow the control block and the problem table
     const size_t off_ictl = align_up(align_up(sizeof(Ctrl), 256) + sizeof(Inst) * (size_t)c.n_inst, 256);
     std::vector<InstCtl> ic((size_t)n);
@@ -510,6 +512,7 @@ int fmm_get_adjoint_stats(const void *workspace, fmm_adjoint_stats *out, void *s
     if (hipMemcpyAsync(&c, workspace, sizeof c, hipMemcpyDeviceToHost, s) != hipSuccess) return FMM_EHIP;
     if (hipStreamSynchronize(s) != hipSuccess) return FMM_EHIP;
     memset(out, 0, sizeof *out);
+    if (c.magic != ADJ_MAGIC) return FMM_EINVAL;
     out->n_points = (int64_t)c.n_points;
     out->n_levels = (int64_t)c.levels;
     out->device_error = c.error;

@@ -52,6 +52,7 @@ struct alignas(128) InstCtl {
 };
 
 constexpr int WORK_SEGS = 8;  // item-list segments, one per XCD
+constexpr uint32_t CTRL_MAGIC = 0x464d4d31u;
 
 struct Ctrl {
     alignas(128) uint32_t bar;  // grid barrier arrivals (monotonic)
@@ -62,6 +63,7 @@ struct Ctrl {
     uint32_t nwg;
     uint32_t tile_edge;
     uint32_t n_inst;  // problems of the last solve
+    uint32_t magic;   // CTRL_MAGIC once a solve has initialised the workspace
     alignas(128) Slot slot[3];
     alignas(128) unsigned long long n_march;
     unsigned long long n_solve;

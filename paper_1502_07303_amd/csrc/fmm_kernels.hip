@@ -1134,6 +1134,7 @@ __global__ void k_init_ws(Params P, int E)
         c->nwg = 0;
         c->tile_edge = (uint32_t)E;
         c->n_inst = P.n_inst;
+        c->magic = CTRL_MAGIC;
         for (int k = 0; k < 3; k++) c->slot[k].live_len = c->slot[k].d_len = 0;
         c->n_march = c->n_solve = c->n_round = c->n_reopen = 0;
         for (int k = 0; k < 16; k++) c->prof[k] = 0;

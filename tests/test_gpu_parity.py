@@ -205,3 +205,16 @@ def test_one_march_per_restart_parity(fmm, oracle_mod, shape, seed):
     To, so, _ = oracle_solve(oracle_mod, w2)
     Tg, sg, st = gpu_solve(fmm, w2, one_march=True)
     assert_parity(Tg, sg, To, so, allow_edge=w2.width)
+
+
+def test_stats_of_unused_workspace(fmm):
+    """A workspace no solve has initialised reports FMM_EINVAL, not garbage."""
+    s = fmm.Solver((16, 16, 16), 1, 0.1, device=torch.device("cuda:0"))
+    s.workspace.zero_()
+    with pytest.raises(fmm.FmmError) as ei:
+        s.stats()
+    assert ei.value.code == fmm.FMM_EINVAL
+    a_ws = torch.zeros(4096, dtype=torch.uint8, device=torch.device("cuda:0"))
+    st = fmm.FmmAdjointStats()
+    rc = fmm.load_library().fmm_get_adjoint_stats(fmm._ptr(a_ws), fmm.ctypes.byref(st), fmm._stream_handle())
+    assert rc == fmm.FMM_EINVAL
