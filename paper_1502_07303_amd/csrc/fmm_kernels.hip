@@ -88,7 +88,11 @@ template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int 
 constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
 constexpr int MAX_ROUNDS = 1 << 16;
 
-enum : uint8_t { FL_SEED = 1, FL_UPD = 2, FL_CHG = 4 };
+// Cell flags.  FL_SRC caches "is a source at the current level" (a seed, or a
+// finite value within the level of its side): set when the tile is loaded,
+// when a value drops to the level and when the level rises.  Values only
+// decrease and the level only rises during a march, so it is never cleared.
+enum : uint8_t { FL_SEED = 1, FL_UPD = 2, FL_CHG = 4, FL_SRC = 8 };
 enum { MODE_INIT = 0, MODE_M1 = 1, MODE_M2 = 2 };
 
 template <int E, typename FT> struct WaveLds {
@@ -277,7 +281,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
             const double a = fabs(v);
             na[2 * ax + s] = a;
             upd |= (fl & FL_UPD) ? (1u << (2 * ax + s)) : 0u;
-            if (a < ap && is_source(v, fl, bnd)) {
+            if (a < ap && (fl & FL_SRC)) {
                 if (v < 0.0)
                     mneg = fmin(mneg, a);
                 else
@@ -348,9 +352,10 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
                 const int d = G::domp(p);
                 if (is_source(vp, 0, th) || fabs(vp) <= (vp < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
                 L.T[d] = nv;
-                L.fl[d] |= FL_CHG;
+                const bool src = is_source(nv, 0, th);
+                L.fl[d] |= src ? (uint8_t)(FL_CHG | FL_SRC) : (uint8_t)FL_CHG;
                 const double a = fabs(nv);
-                if (is_source(nv, 0, th)) {
+                if (src) {
                     if (((upd >> 0) & 1u) && na[0] > a) L.cf[p - E * E] = 1;
                     if (((upd >> 1) & 1u) && na[1] > a) L.cf[p + E * E] = 1;
                     if (((upd >> 2) & 1u) && na[2] > a) L.cf[p - E] = 1;
@@ -400,7 +405,7 @@ __device__ __forceinline__ void band_min(const WaveLds<E, FT> &L, const double t
         if (a <= (v < 0.0 ? th[0] : th[1])) continue;
         face_inner<E>(f, c0, c1, c2);
         const int di = G::dom(c0, c1, c2);
-        if (!(L.fl[di] & FL_UPD) || is_source(L.T[di], 0, th)) continue;
+        if (!(L.fl[di] & FL_UPD) || (L.fl[di] & FL_SRC)) continue;
         if (v < 0.0)
             a0 = fmin(a0, a);
         else
@@ -424,7 +429,10 @@ __device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double
         const double v = L.T[d];
         const double a = fabs(v);
         const int s = v < 0.0 ? 0 : 1;
-        if (a < FMM_INF && a > lo[s] && a <= hi[s]) mark_nbrs(L, p, d, a);
+        if (a < FMM_INF && a > lo[s] && a <= hi[s]) {
+            L.fl[d] |= FL_SRC;
+            mark_nbrs(L, p, d, a);
+        }
     }
     for (int q = lane; q < 6 * FACE; q += 64) {
         const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
@@ -435,6 +443,7 @@ __device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double
         const double a = fabs(v);
         const int s = v < 0.0 ? 0 : 1;
         if (!(a < FMM_INF && a > lo[s] && a <= hi[s]) || (L.fl[d] & FL_SEED)) continue;
+        L.fl[d] |= FL_SRC;
         face_inner<E>(f, c0, c1, c2);
         const int di = G::dom(c0, c1, c2);
         if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > a) L.cf[(c0 * E + c1) * E + c2] = 1;
@@ -492,6 +501,8 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     // grid or for a tile not yet written in an earlier phase.
     constexpr int NI = (V + 63) / 64, NF = (6 * FACE + 63) / 64;
     constexpr int CI = NI < 8 ? NI : 8, CF = NF < 8 ? NF : 8;
+    // the level the march starts at (the sources it loads)
+    const double th0[2] = {mode == MODE_INIT ? -1.0 : lastb[0], mode == MODE_INIT ? -1.0 : lastb[1]};
     for (int j0 = 0; j0 < NI; j0 += CI) {
         double vi[CI];
         FT fi[CI];
@@ -509,9 +520,12 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
             if (p < V) {
                 const int d = G::domp(p);
                 const bool seed = hasSeed && ((mask[p >> 6] >> (p & 63)) & 1ull);
-                L.T[d] = fresh ? FMM_INF : vi[j];
+                const double tv = fresh ? FMM_INF : vi[j];
+                uint8_t f8 = seed ? FL_SEED : ((double)fi[j] > 0.0 ? FL_UPD : 0);
+                if (is_source(tv, f8, th0)) f8 |= FL_SRC;
+                L.T[d] = tv;
                 L.F[p] = fi[j];
-                L.fl[d] = seed ? FL_SEED : ((double)fi[j] > 0.0 ? FL_UPD : 0);
+                L.fl[d] = f8;
                 L.cf[p] = 0;
             }
         }
@@ -568,6 +582,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                     if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
                 }
                 const int d = G::dom(c0, c1, c2);
+                if (is_source(v, fl, th0)) fl |= FL_SRC;
                 L.T[d] = v;
                 L.fl[d] = fl;
             }
