@@ -257,8 +257,10 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 // new signed value if it improves on the current one.  Also hands back what
 // the update step needs without another LDS round trip: the old value, the
 // magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z) and which of them
-// are updatable interior cells.
-template <int E, typename FT, bool AN>
+// are updatable interior cells.  TWO = false is the path for a tile whose
+// values are all on the positive side (no negative value in the tile or its
+// halo, so none can appear): one minimum per axis and one solve.
+template <int E, typename FT, bool AN, bool TWO>
 __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
                                            const double bnd[2], double &out,
                                            double &vp, double na[6], uint32_t &upd)
@@ -266,6 +268,32 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
     using G = Geo<E>;
     const int d = G::domp(p);
     vp = L.T[d];
+    if constexpr (!TWO) {
+        double m[3];
+        upd = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+            const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
+            double mm = FMM_INF;
+#pragma unroll
+            for (int s = 0; s < 2; s++) {
+                const int dn = s ? d + off : d - off;
+                const double v = L.T[dn];
+                const uint8_t fl = L.fl[dn];
+                na[2 * ax + s] = v;
+                upd |= (fl & FL_UPD) ? (1u << (2 * ax + s)) : 0u;
+                if (v < vp && (fl & FL_SRC)) mm = fmin(mm, v);
+            }
+            m[ax] = mm;
+        }
+        if (!(fmin(m[0], fmin(m[1], m[2])) < FMM_INF)) return false;
+        const double r = h / (double)L.F[p];
+        int kk;
+        const double u = AN ? godunov_w_sel(m[0], m[1], m[2], sp.s[0], sp.s[1], sp.s[2], r, &kk)
+                            : godunov_sel(m[0], m[1], m[2], r, &kk);
+        out = u;
+        return u < vp;
+    }
     const double ap = fabs(vp);
     double am[3], ap3[3];  // per-axis minima for side - and side +
     upd = 0;
@@ -323,7 +351,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
 // Neighbours are marked from the magnitudes the evaluation read; values only
 // decrease, so a neighbour lowered meanwhile is at worst marked needlessly,
 // never missed.
-template <int E, typename FT, bool AN>
+template <int E, typename FT, bool AN, bool TWO>
 __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double h, const double th[2], const double lastb[2],
                                      WaveState &ws)
 {
@@ -344,7 +372,7 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             int p = 0;
             if (k < n) {
                 p = L.list[k];
-                ch = eval_point<E, FT, AN>(L, P.sp, p, h, th, nv, vp, na, upd);
+                ch = eval_point<E, FT, AN, TWO>(L, P.sp, p, h, th, nv, vp, na, upd);
                 ws.n_solve++;
             }
             wave_sync();
@@ -503,6 +531,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     constexpr int CI = NI < 8 ? NI : 8, CF = NF < 8 ? NF : 8;
     // the level the march starts at (the sources it loads)
     const double th0[2] = {mode == MODE_INIT ? -1.0 : lastb[0], mode == MODE_INIT ? -1.0 : lastb[1]};
+    bool anyneg = false;  // a negative value in the tile or its halo
     for (int j0 = 0; j0 < NI; j0 += CI) {
         double vi[CI];
         FT fi[CI];
@@ -523,6 +552,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 const double tv = fresh ? FMM_INF : vi[j];
                 uint8_t f8 = seed ? FL_SEED : ((double)fi[j] > 0.0 ? FL_UPD : 0);
                 if (is_source(tv, f8, th0)) f8 |= FL_SRC;
+                anyneg |= tv < 0.0;
                 L.T[d] = tv;
                 L.F[p] = fi[j];
                 L.fl[d] = f8;
@@ -583,12 +613,14 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 }
                 const int d = G::dom(c0, c1, c2);
                 if (is_source(v, fl, th0)) fl |= FL_SRC;
+                anyneg |= v < 0.0;
                 L.T[d] = v;
                 L.fl[d] = fl;
             }
         }
     }
     if (lane < 12) L.bm[lane] = bits_of(FMM_INF);
+    const bool two = __ballot(anyneg) != 0ull;  // both sides present: the general relaxation
     wave_sync();
 
     // ---- ordered relaxation.  Sources at level th are the seeds and the
@@ -637,7 +669,8 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     PROF_ADD(3, t_marked - t_loaded);
     for (;;) {
         PROF_CLOCK(t_r0);
-        rounds += relax<E, FT, AN>(P, L, G0.h, th, lastb, ws);
+        rounds += two ? relax<E, FT, AN, true>(P, L, G0.h, th, lastb, ws)
+                      : relax<E, FT, AN, false>(P, L, G0.h, th, lastb, ws);
         PROF_CLOCK(t_r1);
         PROF_ADD(4, t_r1 - t_r0);
         PROF_ADD(8, 1);
