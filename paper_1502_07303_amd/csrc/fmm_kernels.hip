@@ -99,7 +99,7 @@ template <int E, typename FT> struct WaveLds {
     double T[Geo<E>::DV];                 // domain values (interior + face halos)
     FT F[Geo<E>::V];                      // interior speeds
     uint16_t list[Geo<E>::V];             // candidate list (interior indices)
-    alignas(8) uint8_t cf[Geo<E>::V];     // candidate flags (interior indices)
+    alignas(8) uint8_t cf[Geo<E>::V + 8]; // candidate flags (interior indices); cf[V] takes unwanted marks
     uint8_t fl[Geo<E>::DV];               // FL_* per domain cell
     uint32_t stL[STAGE];                  // staged live-list appends
     uint32_t stD[STAGE];                  // staged dirty-list appends
@@ -378,18 +378,24 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             wave_sync();
             if (ch) {
                 const int d = G::domp(p);
-                if (is_source(vp, 0, th) || fabs(vp) <= (vp < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
+                const uint8_t fo = L.fl[d];
+                // reopened: the old value was already a source, or within the
+                // bound of the tile's previous march
+                if ((fo & FL_SRC) || fabs(vp) <= (vp < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
                 L.T[d] = nv;
                 const bool src = is_source(nv, 0, th);
-                L.fl[d] |= src ? (uint8_t)(FL_CHG | FL_SRC) : (uint8_t)FL_CHG;
+                L.fl[d] = fo | (src ? (uint8_t)(FL_CHG | FL_SRC) : (uint8_t)FL_CHG);
                 const double a = fabs(nv);
                 if (src) {
-                    if (((upd >> 0) & 1u) && na[0] > a) L.cf[p - E * E] = 1;
-                    if (((upd >> 1) & 1u) && na[1] > a) L.cf[p + E * E] = 1;
-                    if (((upd >> 2) & 1u) && na[2] > a) L.cf[p - E] = 1;
-                    if (((upd >> 3) & 1u) && na[3] > a) L.cf[p + E] = 1;
-                    if (((upd >> 4) & 1u) && na[4] > a) L.cf[p - 1] = 1;
-                    if (((upd >> 5) & 1u) && na[5] > a) L.cf[p + 1] = 1;
+                    // mark the downwind updatable neighbours; the others write
+                    // the spare flag cf[V] (no branches)
+                    constexpr int V = G::V;
+                    L.cf[(((upd >> 0) & 1u) && na[0] > a) ? p - E * E : V] = 1;
+                    L.cf[(((upd >> 1) & 1u) && na[1] > a) ? p + E * E : V] = 1;
+                    L.cf[(((upd >> 2) & 1u) && na[2] > a) ? p - E : V] = 1;
+                    L.cf[(((upd >> 3) & 1u) && na[3] > a) ? p + E : V] = 1;
+                    L.cf[(((upd >> 4) & 1u) && na[4] > a) ? p - 1 : V] = 1;
+                    L.cf[(((upd >> 5) & 1u) && na[5] > a) ? p + 1 : V] = 1;
                 }
             }
             wave_sync();
