@@ -259,7 +259,11 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 // magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z) and which of them
 // are updatable interior cells.  TWO = false is the path for a tile whose
 // values are all on the positive side (no negative value in the tile or its
-// halo, so none can appear): one minimum per axis and one solve.
+// halo, so none can appear): one minimum per axis and one solve.  That path
+// takes the per-axis minimum over all source neighbours, upwind or not: a
+// neighbour value a >= vp only adds roots above a (strict causality), which
+// cannot beat vp, so every accepted improvement equals the solve over the
+// upwind neighbours alone.
 template <int E, typename FT, bool AN, bool TWO>
 __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
                                            const double bnd[2], double &out,
@@ -281,8 +285,8 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
                 const double v = L.T[dn];
                 const uint8_t fl = L.fl[dn];
                 na[2 * ax + s] = v;
-                upd |= (fl & FL_UPD) ? (1u << (2 * ax + s)) : 0u;
-                if (v < vp && (fl & FL_SRC)) mm = fmin(mm, v);
+                upd |= (uint32_t)((fl >> 1) & 1u) << (2 * ax + s);  // FL_UPD
+                if (fl & FL_SRC) mm = fmin(mm, v);
             }
             m[ax] = mm;
         }
@@ -308,7 +312,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
             const uint8_t fl = L.fl[dn];
             const double a = fabs(v);
             na[2 * ax + s] = a;
-            upd |= (fl & FL_UPD) ? (1u << (2 * ax + s)) : 0u;
+            upd |= (uint32_t)((fl >> 1) & 1u) << (2 * ax + s);  // FL_UPD
             if (a < ap && (fl & FL_SRC)) {
                 if (v < 0.0)
                     mneg = fmin(mneg, a);
@@ -352,8 +356,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
 // decrease, so a neighbour lowered meanwhile is at worst marked needlessly,
 // never missed.
 template <int E, typename FT, bool AN, bool TWO>
-__device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double h, const double th[2], const double lastb[2],
-                                     WaveState &ws)
+__device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double h, const double th[2], WaveState &ws)
 {
     using G = Geo<E>;
     const int lane = threadIdx.x & 63;
@@ -379,13 +382,15 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
             if (ch) {
                 const int d = G::domp(p);
                 const uint8_t fo = L.fl[d];
-                // reopened: the old value was already a source, or within the
-                // bound of the tile's previous march
-                if ((fo & FL_SRC) || fabs(vp) <= (vp < 0.0 ? lastb[0] : lastb[1])) ws.n_reopen++;
+                // reopened: the old value was already a source.  The level
+                // never drops below the bound of the tile's previous march, so
+                // this covers every value that march released.
+                ws.n_reopen += (fo >> 3) & 1u;  // FL_SRC
                 L.T[d] = nv;
-                const bool src = is_source(nv, 0, th);
+                // one-sided tiles: nv is positive and finite (it beat vp)
+                const bool src = TWO ? is_source(nv, 0, th) : nv <= th[1];
                 L.fl[d] = fo | (src ? (uint8_t)(FL_CHG | FL_SRC) : (uint8_t)FL_CHG);
-                const double a = fabs(nv);
+                const double a = TWO ? fabs(nv) : nv;
                 if (src) {
                     // mark the downwind updatable neighbours; the others write
                     // the spare flag cf[V] (no branches)
@@ -675,8 +680,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     PROF_ADD(3, t_marked - t_loaded);
     for (;;) {
         PROF_CLOCK(t_r0);
-        rounds += two ? relax<E, FT, AN, true>(P, L, G0.h, th, lastb, ws)
-                      : relax<E, FT, AN, false>(P, L, G0.h, th, lastb, ws);
+        rounds += two ? relax<E, FT, AN, true>(P, L, G0.h, th, ws) : relax<E, FT, AN, false>(P, L, G0.h, th, ws);
         PROF_CLOCK(t_r1);
         PROF_ADD(4, t_r1 - t_r0);
         PROF_ADD(8, 1);
