@@ -260,10 +260,13 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 // are updatable interior cells.  TWO = false is the path for a tile whose
 // values are all on the positive side (no negative value in the tile or its
 // halo, so none can appear): one minimum per axis and one solve.  That path
-// takes the per-axis minimum over all source neighbours, upwind or not: a
-// neighbour value a >= vp only adds roots above a (strict causality), which
-// cannot beat vp, so every accepted improvement equals the solve over the
-// upwind neighbours alone.
+// takes the per-axis minimum over all neighbours, sources or not, upwind or
+// not.  A neighbour value a >= vp only adds roots above a (strict causality),
+// which cannot beat vp.  A band value below vp is an upper bound of its final
+// value, and the local solver is monotone in its inputs, so the result is
+// still an upper bound of the final value at p; when that neighbour later
+// becomes a source with a smaller value it marks p again, so the fixed point
+// (the discrete system of Eq. 2-3) is the same.
 template <int E, typename FT, bool AN, bool TWO>
 __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
                                            const double bnd[2], double &out,
@@ -286,7 +289,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
                 const uint8_t fl = L.fl[dn];
                 na[2 * ax + s] = v;
                 upd |= (uint32_t)((fl >> 1) & 1u) << (2 * ax + s);  // FL_UPD
-                if (fl & FL_SRC) mm = fmin(mm, v);
+                mm = v < mm ? v : mm;
             }
             m[ax] = mm;
         }
