@@ -281,19 +281,15 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
             const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
-            double mm = FMM_INF;
 #pragma unroll
             for (int s = 0; s < 2; s++) {
                 const int dn = s ? d + off : d - off;
-                const double v = L.T[dn];
-                const uint8_t fl = L.fl[dn];
-                na[2 * ax + s] = v;
-                upd |= (uint32_t)((fl >> 1) & 1u) << (2 * ax + s);  // FL_UPD
-                mm = v < mm ? v : mm;
+                na[2 * ax + s] = L.T[dn];
+                upd |= (uint32_t)((L.fl[dn] >> 1) & 1u) << (2 * ax + s);  // FL_UPD
             }
-            m[ax] = mm;
+            m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
         }
-        if (!(fmin(m[0], fmin(m[1], m[2])) < FMM_INF)) return false;
+        // no finite neighbour: the solver returns +inf, which never beats vp
         const double r = h / (double)L.F[p];
         int kk;
         const double u = AN ? godunov_w_sel(m[0], m[1], m[2], sp.s[0], sp.s[1], sp.s[2], r, &kk)
