@@ -255,9 +255,8 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 
 // Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
 // new signed value if it improves on the current one.  Also hands back what
-// the update step needs without another LDS round trip: the old value, the
-// magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z) and which of them
-// are updatable interior cells.  TWO = false is the path for a tile whose
+// the update step needs without another LDS round trip: the old value and the
+// magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z).  TWO = false is the path for a tile whose
 // values are all on the positive side (no negative value in the tile or its
 // halo, so none can appear): one minimum per axis and one solve.  That path
 // takes the per-axis minimum over all neighbours, sources or not, upwind or
@@ -270,23 +269,18 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 template <int E, typename FT, bool AN, bool TWO>
 __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
                                            const double bnd[2], double &out,
-                                           double &vp, double na[6], uint32_t &upd)
+                                           double &vp, double na[6])
 {
     using G = Geo<E>;
     const int d = G::domp(p);
     vp = L.T[d];
     if constexpr (!TWO) {
         double m[3];
-        upd = 0;
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
             const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
-#pragma unroll
-            for (int s = 0; s < 2; s++) {
-                const int dn = s ? d + off : d - off;
-                na[2 * ax + s] = L.T[dn];
-                upd |= (uint32_t)((L.fl[dn] >> 1) & 1u) << (2 * ax + s);  // FL_UPD
-            }
+            na[2 * ax] = L.T[d - off];
+            na[2 * ax + 1] = L.T[d + off];
             m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
         }
         // no finite neighbour: the solver returns +inf, which never beats vp
@@ -299,7 +293,6 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
     }
     const double ap = fabs(vp);
     double am[3], ap3[3];  // per-axis minima for side - and side +
-    upd = 0;
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
         const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
@@ -311,7 +304,6 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
             const uint8_t fl = L.fl[dn];
             const double a = fabs(v);
             na[2 * ax + s] = a;
-            upd |= (uint32_t)((fl >> 1) & 1u) << (2 * ax + s);  // FL_UPD
             if (a < ap && (fl & FL_SRC)) {
                 if (v < 0.0)
                     mneg = fmin(mneg, a);
@@ -369,12 +361,11 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
         for (int base = 0; base < n; base += 64) {
             const int k = base + lane;
             double nv = 0.0, vp = 0.0, na[6];
-            uint32_t upd = 0;
             bool ch = false;
             int p = 0;
             if (k < n) {
                 p = L.list[k];
-                ch = eval_point<E, FT, AN, TWO>(L, P.sp, p, h, th, nv, vp, na, upd);
+                ch = eval_point<E, FT, AN, TWO>(L, P.sp, p, h, th, nv, vp, na);
                 ws.n_solve++;
             }
             wave_sync();
@@ -391,15 +382,18 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
                 L.fl[d] = fo | (src ? (uint8_t)(FL_CHG | FL_SRC) : (uint8_t)FL_CHG);
                 const double a = TWO ? fabs(nv) : nv;
                 if (src) {
-                    // mark the downwind updatable neighbours; the others write
-                    // the spare flag cf[V] (no branches)
+                    // mark the downwind interior neighbours; the others write
+                    // the spare flag cf[V] (no branches).  Seeds and
+                    // impassable cells may be marked too: their LDS speed is
+                    // 0, so their solve gives +inf and changes nothing.
                     constexpr int V = G::V;
-                    L.cf[(((upd >> 0) & 1u) && na[0] > a) ? p - E * E : V] = 1;
-                    L.cf[(((upd >> 1) & 1u) && na[1] > a) ? p + E * E : V] = 1;
-                    L.cf[(((upd >> 2) & 1u) && na[2] > a) ? p - E : V] = 1;
-                    L.cf[(((upd >> 3) & 1u) && na[3] > a) ? p + E : V] = 1;
-                    L.cf[(((upd >> 4) & 1u) && na[4] > a) ? p - 1 : V] = 1;
-                    L.cf[(((upd >> 5) & 1u) && na[5] > a) ? p + 1 : V] = 1;
+                    const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
+                    L.cf[(i0 > 0 && na[0] > a) ? p - E * E : V] = 1;
+                    L.cf[(i0 < E - 1 && na[1] > a) ? p + E * E : V] = 1;
+                    L.cf[(i1 > 0 && na[2] > a) ? p - E : V] = 1;
+                    L.cf[(i1 < E - 1 && na[3] > a) ? p + E : V] = 1;
+                    L.cf[(i2 > 0 && na[4] > a) ? p - 1 : V] = 1;
+                    L.cf[(i2 < E - 1 && na[5] > a) ? p + 1 : V] = 1;
                 }
             }
             wave_sync();
@@ -564,7 +558,9 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 if (is_source(tv, f8, th0)) f8 |= FL_SRC;
                 anyneg |= tv < 0.0;
                 L.T[d] = tv;
-                L.F[p] = fi[j];
+                // seeds and impassable cells (F <= 0 or NaN) keep speed 0 in
+                // LDS: r = h/0 = +inf, so the relaxation never changes them
+                L.F[p] = (seed || !((double)fi[j] > 0.0)) ? (FT)0 : fi[j];
                 L.fl[d] = f8;
                 L.cf[p] = 0;
             }
