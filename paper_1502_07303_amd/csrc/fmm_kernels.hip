@@ -717,8 +717,17 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         if (i2 == 0) P.Zf[((size_t)t * 2 + 0) * FACE + i0 * E + i1] = v;
         if (i2 == E - 1) P.Zf[((size_t)t * 2 + 1) * FACE + i0 * E + i1] = v;
         if (!chg) continue;
-        const uint32_t fm = (i0 == 0 ? 1u : 0u) | (i0 == E - 1 ? 2u : 0u) | (i1 == 0 ? 4u : 0u) |
-                            (i1 == E - 1 ? 8u : 0u) | (i2 == 0 ? 16u : 0u) | (i2 == E - 1 ? 32u : 0u);
+        // faces this boundary cell lies on whose neighbouring cell it can
+        // improve: the halo holds that cell's value as loaded, an upper bound
+        // of its current value (values only decrease), and a root from v
+        // exceeds |v|; so |v| >= the halo magnitude means nothing to send
+        const double av = fabs(v);
+        const uint32_t fm = (i0 == 0 && av < fabs(L.T[d - G::OX]) ? 1u : 0u) |
+                            (i0 == E - 1 && av < fabs(L.T[d + G::OX]) ? 2u : 0u) |
+                            (i1 == 0 && av < fabs(L.T[d - G::OY]) ? 4u : 0u) |
+                            (i1 == E - 1 && av < fabs(L.T[d + G::OY]) ? 8u : 0u) |
+                            (i2 == 0 && av < fabs(L.T[d - G::OZ]) ? 16u : 0u) |
+                            (i2 == E - 1 && av < fabs(L.T[d + G::OZ]) ? 32u : 0u);
         if (!fm) continue;
         fany |= fm;
         if (is_source(v, 0, bnd)) {
