@@ -9,25 +9,6 @@ namespace fmm {
 
 #define FMM_INF __builtin_huge_val()
 
-// Minimum and maximum of two FP64 values as single instructions.  fmin/fmax
-// in the default IEEE mode first quiet both inputs (one extra instruction per
-// input loaded from memory); no value here is a signalling NaN (they come
-// from arithmetic, or are finite or infinite), and for quiet NaNs the
-// instructions return the other operand, as fmin/fmax do.  Plain ALU
-// instructions, no memory access.
-__device__ __forceinline__ double dmin(double a, double b)
-{
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double dmax(double a, double b)
-{
-    double r;
-    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-
 // ---------------------------------------------------------------------------
 // Local solver (Alg. 11 with Eqs. 4-7).  a = per-axis upwind values (+inf when
 // an axis has no upwind neighbour), r = h / F.  With a1 <= a2 <= a3:
@@ -41,9 +22,9 @@ __device__ __forceinline__ double dmax(double a, double b)
 // sorted values the returned root uses (0 when there is no upwind value).
 __device__ __forceinline__ double godunov_sel(double x, double y, double z, double r, int *k)
 {
-    double lo = dmin(x, y), hi = dmax(x, y);
-    double a3 = dmax(hi, z), m = dmin(hi, z);
-    double a1 = dmin(lo, m), a2 = dmax(lo, m);
+    double lo = fmin(x, y), hi = fmax(x, y);
+    double a3 = fmax(hi, z), m = fmin(hi, z);
+    double a1 = fmin(lo, m), a2 = fmax(lo, m);
     *k = 0;
     if (!(a1 < FMM_INF)) return FMM_INF;
     double r2 = r * r;

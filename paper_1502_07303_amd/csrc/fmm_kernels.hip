@@ -281,7 +281,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
             const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
             na[2 * ax] = L.T[d - off];
             na[2 * ax + 1] = L.T[d + off];
-            m[ax] = dmin(na[2 * ax], na[2 * ax + 1]);
+            m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
         }
         // no finite neighbour: the solver returns +inf, which never beats vp
         const double r = h / (double)L.F[p];
