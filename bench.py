@@ -380,7 +380,11 @@ def main():
                   "tile_marches": int(stats.n_tile_marches), "solves": int(stats.n_solves),
                   "rounds": int(stats.n_rounds), "reopened": int(stats.n_reopened),
                   "workgroups": int(stats.n_workgroups), "max_abs_T": stats.max_abs_T,
-                  "ms_prepare": round(stats.ms_prepare, 4), "ms_finalize": round(stats.ms_finalize, 4)},
+                  "ms_prepare": round(stats.ms_prepare, 4), "ms_finalize": round(stats.ms_finalize, 4),
+                  "ms_solve": {"mean": round(ms, 4), "median": round(float(np.median(times)), 4),
+                               "min": round(float(np.min(times)), 4), "max": round(float(np.max(times)), 4)},
+                  "ms_driver": {"mean": round(ms_drv, 4), "median": round(float(np.median(drv)), 4),
+                                "min": round(float(np.min(drv)), 4), "max": round(float(np.max(drv)), 4)}},
         "context": "paper: CPU cluster only (Cray XE6, Fortran+MPI); its sequential-time fit implies "
                    "~1.3e5-1.6e5 accepted points/s on one 2014 Opteron core at 1024^3 (not a target)",
     }
