@@ -17,9 +17,10 @@
 //                                                     up to the restart bound
 //   Collect/Exchange/Integrate (Alg. 13-15)         -> owner writes its interior to
 //                                                     HBM and flags the neighbour
-//                                                     tiles whose halo changed; they
-//                                                     re-read the halo in the second
-//                                                     march of the restart
+//                                                     tiles whose halo changed by a
+//                                                     value that can improve them;
+//                                                     they re-read the halo in the
+//                                                     second march of the restart
 // Every floating-point expression of the local solver is written out in the
 // order used by the specification of fmm_eval_godunov(); the file is compiled
 // with -ffp-contract=off so no multiply-add is fused.
