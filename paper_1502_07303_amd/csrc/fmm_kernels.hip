@@ -191,11 +191,15 @@ template <int E, typename FT> __device__ __forceinline__ int compact(WaveLds<E, 
         }
 #pragma unroll
         for (int j = 0; j < K / 8; j++) {
-            unsigned long long y = x[j];
+            // the eight 0/1 bytes as an 8-bit mask: byte k holds bit 8k, and
+            // shifting by 7k moves it to bit k (the other bits land at 9 and up)
+            const uint32_t lo = (uint32_t)x[j], hi = (uint32_t)(x[j] >> 32);
+            uint32_t y = ((lo | (lo >> 7) | (lo >> 14) | (lo >> 21)) & 0xFu) |
+                         (((hi | (hi >> 7) | (hi >> 14) | (hi >> 21)) & 0xFu) << 4);
             while (y) {
-                const int bit = __ffsll((long long)y) - 1;
-                out[pre++] = (uint16_t)(lane * K + j * 8 + (bit >> 3));
-                y &= y - 1;
+                const int bit = __builtin_ctz(y);
+                out[pre++] = (uint16_t)(lane * K + j * 8 + bit);
+                y &= y - 1u;
             }
             if (x[j]) w[j] = 0ull;
         }
