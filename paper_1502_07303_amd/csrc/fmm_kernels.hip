@@ -98,7 +98,7 @@ enum { MODE_INIT = 0, MODE_M1 = 1, MODE_M2 = 2 };
 
 template <int E, typename FT> struct WaveLds {
     double T[Geo<E>::DV];                 // domain values (interior + face halos)
-    FT F[Geo<E>::V];                      // interior speeds
+    FT F[Geo<E>::V];                      // interior speeds (FP32), or h / F (FP64)
     uint16_t list[Geo<E>::V];             // candidate list (interior indices)
     alignas(8) uint8_t cf[Geo<E>::V + 8]; // candidate flags (interior indices); cf[V] takes unwanted marks
     uint8_t fl[Geo<E>::DV];               // FL_* per domain cell
@@ -258,6 +258,16 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
     return a <= (v < 0.0 ? bnd[0] : bnd[1]);
 }
 
+// r = h / F of interior point p (+inf for seeds and impassable cells).
+template <int E, typename FT>
+__device__ __forceinline__ double cell_r(const WaveLds<E, FT> &L, int p, double h)
+{
+    if constexpr (sizeof(FT) == 8)
+        return L.F[p];
+    else
+        return h / (double)L.F[p];
+}
+
 // Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
 // new signed value if it improves on the current one.  Also hands back what
 // the update step needs without another LDS round trip: the old value and the
@@ -289,7 +299,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
             m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
         }
         // no finite neighbour: the solver returns +inf, which never beats vp
-        const double r = h / (double)L.F[p];
+        const double r = cell_r(L, p, h);
         int kk;
         const double u = AN ? godunov_w_sel(m[0], m[1], m[2], sp.s[0], sp.s[1], sp.s[2], r, &kk)
                             : godunov_sel(m[0], m[1], m[2], r, &kk);
@@ -319,7 +329,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
         am[ax] = mneg;
         ap3[ax] = mpos;
     }
-    const double r = h / (double)L.F[p];
+    const double r = cell_r(L, p, h);
     double best = ap;
     bool neg = vp < 0.0;
     bool improved = false;
@@ -564,8 +574,14 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 anyneg |= tv < 0.0;
                 L.T[d] = tv;
                 // seeds and impassable cells (F <= 0 or NaN) keep speed 0 in
-                // LDS: r = h/0 = +inf, so the relaxation never changes them
-                L.F[p] = (seed || !((double)fi[j] > 0.0)) ? (FT)0 : fi[j];
+                // LDS (r = h/0 = +inf), so the relaxation never changes them.
+                // An FP64 slot holds r = h / F itself, computed once per cell
+                // with the same expression as for FP32 speeds.
+                const bool fixed = seed || !((double)fi[j] > 0.0);
+                if constexpr (sizeof(FT) == 8)
+                    L.F[p] = fixed ? FMM_INF : G0.h / (double)fi[j];
+                else
+                    L.F[p] = fixed ? (FT)0 : fi[j];
                 L.fl[d] = f8;
                 L.cf[p] = 0;
             }
