@@ -1255,21 +1255,29 @@ __global__ void k_init_ws(Params P, int E)
 // index of each of its tiles.  One workgroup per tile.
 template <int E, typename FT> __global__ void k_tile_speed(Params P, Inst I, uint32_t j)
 {
+    // A workgroup of E wavefronts takes one slab: a plane i0 (padded to whole
+    // tiles) and one row of tiles along axis 1; wavefront w reads grid row
+    // i1 = E ty + w.  Each row is read contiguously, and together the E
+    // wavefronts fill E x E contiguous values of every tile they cross.
+    // Cells outside the grid get speed 0 (impassable).
     constexpr int V = E * E * E;
     const FT *F = (const FT *)I.F;
     FT *Ft = (FT *)P.Ft;
-    const int64_t n12 = I.n1 * I.n2;
-    for (int64_t tl = blockIdx.x; tl < (int64_t)I.ntiles; tl += gridDim.x) {
-        const int64_t tz = tl % I.t2, ty = (tl / I.t2) % I.t1, tx = tl / ((int64_t)I.t2 * I.t1);
-        const size_t t = (size_t)I.base + (size_t)tl;
-        for (int p = threadIdx.x; p < V; p += blockDim.x) {
-            const int i0 = p / (E * E), i1 = (p / E) % E, i2 = p % E;
-            const int64_t g0 = tx * E + i0, g1 = ty * E + i1, g2 = tz * E + i2;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n12 = I.n1 * I.n2, slabs = (int64_t)I.t0 * E * I.t1, len2 = (int64_t)I.t2 * E;
+    for (int64_t sl = blockIdx.x; sl < slabs; sl += gridDim.x) {
+        const int64_t i0 = sl / I.t1, ty = sl - i0 * I.t1, i1 = ty * E + w;
+        const bool row_in = i0 < I.n0 && i1 < I.n1;
+        const size_t trow = (size_t)I.base + (size_t)(((i0 / E) * I.t1 + ty) * I.t2);
+        const int prow = (int)(((i0 % E) * E + w) * E);
+        for (int64_t i2 = lane; i2 < len2; i2 += 64) {
             FT f = (FT)0;
-            if (g0 < I.n0 && g1 < I.n1 && g2 < I.n2) f = F[g0 * n12 + g1 * I.n2 + g2];
-            Ft[t * V + p] = f;
+            if (row_in && i2 < I.n2) f = F[i0 * n12 + i1 * I.n2 + i2];
+            const size_t t = trow + (size_t)(i2 / E);
+            Ft[t * V + prow + (int)(i2 % E)] = f;
+            if (prow == 0 && i2 % E == 0) P.tinst[t] = j;
         }
-        if (threadIdx.x == 0) P.tinst[t] = j;
     }
 }
 
@@ -1384,47 +1392,52 @@ template <typename FT> __global__ void k_validate(Params P, Inst I)
 
 // ---------------------------------------------------------------------------
 // Finalize one problem: row-major T (accepted points and seeds keep their
-// values, all others +inf), status bytes and statistics.  Each thread
-// handles one grid point; a block covers a run of a grid row.
+// values, all others +inf), status bytes and statistics.  A workgroup of E
+// wavefronts takes a slab (a plane i0 and one row of tiles along axis 1);
+// wavefront w writes grid row i1 = E ty + w, so the E wavefronts together read
+// E x E contiguous values of every tile they cross.
 
 template <int E> __global__ void k_finalize(Params P, Inst I, uint32_t j)
 {
     constexpr int V = E * E * E;
-    const int64_t rows = I.n0 * I.n1;
-    const int64_t chunks = (I.n2 + blockDim.x - 1) / blockDim.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t slabs = I.n0 * I.t1;
     unsigned long long acc = 0;
     double mx = 0.0;
-    for (int64_t wi = blockIdx.x; wi < rows * chunks; wi += gridDim.x) {
-        const int64_t row = wi / chunks, ch = wi - row * chunks;
-        const int64_t i2 = ch * blockDim.x + threadIdx.x;
-        if (i2 >= I.n2) continue;
-        const int64_t i0 = row / I.n1, i1 = row - i0 * I.n1;
-        const int64_t g = row * I.n2 + i2;
-        const uint32_t t = I.base + (uint32_t)(((i0 / E) * I.t1 + i1 / E) * I.t2 + i2 / E);
-        const int p = (int)(((i0 % E) * E + i1 % E) * E + i2 % E);
-        bool seed = false;
-        if (P.tflags[t] & TF_SEED) seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
-        const double v = P.visit[t] ? P.Tt[(size_t)t * V + p] : FMM_INF;
-        const double a = fabs(v);
-        const uint8_t neg = v < 0.0 ? 0x80 : 0;
-        uint8_t st;
-        double out = FMM_INF;
-        if (seed) {
-            st = 3 | neg;
-            out = v;
-            mx = fmax(mx, a);
-        } else if (a < FMM_INF && a <= P.width) {
-            st = 2 | neg;
-            out = v;
-            acc++;
-            mx = fmax(mx, a);
-        } else if (a < FMM_INF) {
-            st = 1 | neg;
-        } else {
-            st = 0;
+    for (int64_t sl = blockIdx.x; sl < slabs; sl += gridDim.x) {
+        const int64_t i0 = sl / I.t1, ty = sl - i0 * I.t1, i1 = ty * E + wv;
+        if (i1 >= I.n1) continue;
+        const int64_t row = i0 * I.n1 + i1;
+        const uint32_t trow = I.base + (uint32_t)(((i0 / E) * I.t1 + ty) * I.t2);
+        const int prow = (int)(((i0 % E) * E + wv) * E);
+        for (int64_t i2 = threadIdx.x & 63; i2 < I.n2; i2 += 64) {
+            const int64_t g = row * I.n2 + i2;
+            const uint32_t t = trow + (uint32_t)(i2 / E);
+            const int p = prow + (int)(i2 % E);
+            bool seed = false;
+            if (P.tflags[t] & TF_SEED) seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
+            const double v = P.visit[t] ? P.Tt[(size_t)t * V + p] : FMM_INF;
+            const double a = fabs(v);
+            const uint8_t neg = v < 0.0 ? 0x80 : 0;
+            uint8_t st;
+            double out = FMM_INF;
+            if (seed) {
+                st = 3 | neg;
+                out = v;
+                mx = fmax(mx, a);
+            } else if (a < FMM_INF && a <= P.width) {
+                st = 2 | neg;
+                out = v;
+                acc++;
+                mx = fmax(mx, a);
+            } else if (a < FMM_INF) {
+                st = 1 | neg;
+            } else {
+                st = 0;
+            }
+            I.T[g] = out;
+            if (I.status) I.status[g] = st;
         }
-        I.T[g] = out;
-        if (I.status) I.status[g] = st;
     }
     __shared__ unsigned long long s_acc[16];
     __shared__ double s_mx[16];
@@ -1482,11 +1495,12 @@ template <int E> static hipError_t launch_prepare_t(const Params &P, const Inst 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int64_t j = 0; j < n; j++) {
         const Inst &I = insts[j];
-        const unsigned tb = (unsigned)std::min<int64_t>((int64_t)I.ntiles, (int64_t)cus * 32);
+        const int64_t slabs = (int64_t)I.t0 * E * I.t1;
+        const unsigned tb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(slabs, (int64_t)cus * 8));
         if (f64)
-            hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(256), 0, s, P, I, (uint32_t)j);
+            hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(64 * E), 0, s, P, I, (uint32_t)j);
         else
-            hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(256), 0, s, P, I, (uint32_t)j);
+            hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(64 * E), 0, s, P, I, (uint32_t)j);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     bool any_seeds = false;
@@ -1590,9 +1604,9 @@ template <int E> static hipError_t launch_finalize_t(const Params &P, const Inst
     const int cus = num_cus();
     for (int64_t j = 0; j < n; j++) {
         const Inst &I = insts[j];
-        const int64_t rows = I.n0 * I.n1 * ((I.n2 + 255) / 256);
-        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(rows, (int64_t)cus * 16));
-        hipLaunchKernelGGL(k_finalize<E>, dim3(blocks), dim3(256), 0, s, P, I, (uint32_t)j);
+        const int64_t slabs = I.n0 * I.t1;
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(slabs, (int64_t)cus * 8));
+        hipLaunchKernelGGL(k_finalize<E>, dim3(blocks), dim3(64 * E), 0, s, P, I, (uint32_t)j);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
