@@ -57,12 +57,39 @@ def read_traffic(kernel_tag, stride_h):
         return None
 
 
+def _code_only(text):
+    """C++ source without comments, string literals kept, and without blank
+    lines or trailing spaces: the tag follows the code, not its comments."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = [l.rstrip() for l in "".join(out).split("\n")]
+    return "\n".join(l for l in lines if l)
+
+
 def kernel_tag():
+    """Hash of the driver's sources (code only), tying the committed HBM
+    counter summary to the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
     for f in ("fmm_kernels.hip", "fmm_internal.h", "fmm_device.h", "fmm_api.cpp"):
-        with open(os.path.join(ROOT, "paper_1502_07303_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1502_07303_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -271,9 +271,10 @@ __device__ __forceinline__ double cell_r(const WaveLds<E, FT> &L, int p, double 
 // Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
 // new signed value if it improves on the current one.  Also hands back what
 // the update step needs without another LDS round trip: the old value and the
-// magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z).  TWO = false is the path for a tile whose
-// values are all on the positive side (no negative value in the tile or its
-// halo, so none can appear): one minimum per axis and one solve.  That path
+// magnitudes of the six neighbours (order -x,+x,-y,+y,-z,+z).
+// TWO = false is the path for a tile whose values are all on the positive
+// side (no negative value in the tile or its halo, so none can appear): one
+// minimum per axis and one solve.  That path
 // takes the per-axis minimum over all neighbours, sources or not, upwind or
 // not.  A neighbour value a >= vp only adds roots above a (strict causality),
 // which cannot beat vp.  A band value below vp is an upper bound of its final
