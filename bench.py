@@ -4,7 +4,7 @@
 Default workload: the 1024^3 full-domain march with an FP32 random speed field
 (F = clip(exp(0.5 g), 0.25, 4), g a Gaussian field with correlation length
 0.05) and four point sources, FP64 arithmetic, 8^3 tiles, the restart stride
-swept by the library's autotuner (2h to 5h by default).
+swept by the library's autotuner (3h, 4h and 5h by default).
 Prints one JSON line: accepted grid points per second of the whole solve with
 inputs resident in HBM, the roofline of the restart driver (the dominant
 kernel) and a CPU baseline from the oracle on a bounded sample.
