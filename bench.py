@@ -244,6 +244,39 @@ def adjoint_vs_forward(fmm, inputs, dev, steps):
                       "stride 2h), adjoint = fmm_adjoint_batch of the 16 shots into one dL/dF"}
 
 
+def stride_table(fmm, w, spec, T, status):
+    """Driver time of the same solve for each (tile edge, restart stride) of
+    ``spec`` ("edge:s1,s2,...;edge:..." with strides in units of h, 'inf'
+    allowed): two solves each, the minimum, with the solve statistics."""
+    out = {}
+    for part in spec.split(";"):
+        e_s, strides = part.split(":")
+        e = int(e_s)
+        for sh in (float(x) for x in strides.split(",")):
+            sv = fmm.Solver(w.shape, w.seed_idx.numel(), w.h, band_width=w.width, stride=sh * w.h,
+                            tile_edge=e, timing=True, time_limit_s=60, device=w.F.device,
+                            speed_dtype=w.F.dtype)
+            best, st = None, None
+            key = f"E{e} {sh:g}h"
+            try:
+                for _ in range(2):
+                    sv.solve_into(w.F, w.seed_idx, w.seed_val, T, status)
+                    st = sv.stats()
+                    best = st.ms_driver if best is None else min(best, st.ms_driver)
+            except fmm.FmmError as ex:  # e.g. the 60 s time limit
+                out[key] = {"error": str(ex)}
+                log(f"  table {key}: {ex}")
+                del sv
+                continue
+            out[key] = {"driver_ms": round(best, 2), "restarts": int(st.n_restarts),
+                        "tile_marches": int(st.n_tile_marches),
+                        "solves_per_point": round(st.n_solves / st.n_accepted, 2)}
+            log(f"  table {key}: driver {best:.2f} ms, restarts {st.n_restarts}, "
+                f"marches {st.n_tile_marches}, solves/pt {st.n_solves / st.n_accepted:.2f}")
+            del sv
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +292,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-serial measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward measurement")
+    ap.add_argument("--table", default=None,
+                    help="also time a tile-edge x stride table on the same workload, e.g. "
+                         "'8:0.5,2,4,inf;4:2,4' (edge: strides in units of h); two solves each, minimum")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GiB for a plain device copy, timed as achievable-HBM context and used to "
                          "calibrate HBM byte counters")
@@ -355,7 +391,11 @@ def main():
     if traffic is not None:
         roofline["traffic_GBs"] = round(traffic / (ms_drv / 1e3) / 1e9, 2)
 
-    del solver, T, status
+    del solver
+    table = None
+    if args.table:
+        table = stride_table(fmm, w, args.table, T, status)
+    del T, status
     torch.cuda.empty_cache()
     batch = None
     if not args.no_batch:
@@ -402,6 +442,7 @@ def main():
         "cpu_baseline": cpu,
         "hbm_copy_probe": copy_probe,
         "batch_vs_serial": batch,
+        "stride_table": table,
         "adjoint_vs_forward": adj,
         "solve": {"accepted": n_acc, "points": N, "restarts": int(stats.n_restarts),
                   "tile_marches": int(stats.n_tile_marches), "solves": int(stats.n_solves),
