@@ -948,9 +948,11 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             continue;
         }
         if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
-        if (ld_acq(&c->abort)) break;
+        // the item and the abort flag are requested together (one round trip)
         const uint32_t i = lo + k;
-        const uint32_t t = __builtin_amdgcn_readfirstlane(items[i]);
+        const uint32_t item = items[i];
+        if (ld_acq(&c->abort)) break;
+        const uint32_t t = __builtin_amdgcn_readfirstlane(item);
         const uint32_t j = P.n_inst == 1 ? 0u : __builtin_amdgcn_readfirstlane(P.tinst[t]);
         if (j != iv.j) load_inst(P, j, r, mode, iv);
         // a problem that passed its exit test takes no further part
