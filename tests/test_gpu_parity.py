@@ -218,3 +218,22 @@ def test_stats_of_unused_workspace(fmm):
     st = fmm.FmmAdjointStats()
     rc = fmm.load_library().fmm_get_adjoint_stats(fmm._ptr(a_ws), fmm.ctypes.byref(st), fmm._stream_handle())
     assert rc == fmm.FMM_EINVAL
+
+
+@pytest.mark.parametrize("stride_h", [0.5, 4.0, math.inf])
+def test_stats_consistent(fmm, stride_h):
+    """The solve counters obey bounds every correct run meets: each accepted
+    non-seed point was solved at least once, a reopened value is a solve that
+    improved a released value, every march does at least one round of work or
+    none, and a solve needs at least the two restarts that start and end the
+    loop."""
+    w = inputs.random_small((37, 29, 45), n_sources=3, seed=1, dtype=torch.float32)
+    Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h)
+    assert st.n_accepted == int(np.sum((sg & 3) == 2))
+    assert st.n_solves >= st.n_accepted
+    assert 0 <= st.n_reopened <= st.n_solves
+    tiles = math.ceil(37 / 8) * math.ceil(29 / 8) * math.ceil(45 / 8)
+    assert st.n_tile_marches >= tiles
+    assert st.n_rounds <= st.n_solves
+    assert st.n_restarts >= 2
+    assert st.max_abs_T == float(np.max(np.abs(Tg[(sg & 3) >= 2])))

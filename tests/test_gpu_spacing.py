@@ -28,10 +28,13 @@ def fmm():
 
 @pytest.mark.parametrize("sc", SCALES)
 @pytest.mark.parametrize("edge", [4, 8])
-def test_spacing_parity(fmm, oracle_mod, sc, edge):
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_spacing_parity(fmm, oracle_mod, sc, edge, dtype):
+    """FP64 and FP32 speeds take different march instantiations (FP64 tiles
+    hold r = h/F in LDS, FP32 tiles divide per solve)."""
     dev = torch.device("cuda:0")
     for shape, seed, zero in (((37, 29, 45), 1, 0.0), ((33, 40, 18), 2, 0.08)):
-        w = inputs.random_small(shape, n_sources=2, seed=seed, zero_frac=zero)
+        w = inputs.random_small(shape, n_sources=2, seed=seed, zero_frac=zero, dtype=dtype)
         F, idx, val = w.numpy()
         To, so, _, _ = oracle_mod.solve(F, w.h, idx, val, axis_scale=sc)
         for stride_h in (0.5, 2.0, math.inf):
