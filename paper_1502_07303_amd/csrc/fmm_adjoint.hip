@@ -89,6 +89,9 @@ __device__ __forceinline__ uint32_t upwind_code(const AdjInst &I, int64_t p, int
     return code;
 }
 
+// Counter offset of points outside the linear system (see k_adj_setup).
+constexpr uint32_t ADJ_FIXED_COUNT = 1u << 30;
+
 // Reset: accumulators, counters and codes of every problem.
 __global__ void k_adj_zero(AdjParams P, AdjInst I)
 {
@@ -109,7 +112,13 @@ template <typename FT> __global__ void k_adj_setup(AdjParams P, AdjInst I)
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i0 = p / n12, rem = p - i0 * n12, i1 = rem / I.n2, i2 = rem - i1 * I.n2;
         const uint32_t code = upwind_code<FT>(I, p, i0, i1, i2);
-        if (!code) continue;
+        if (!code) {
+            // a fixed point (seed or outside the accepted set): its counter
+            // starts far above the at most six decrements it can receive, so
+            // it never reaches zero and never joins a frontier
+            atomicAdd(&P.cnt[I.base + p], ADJ_FIXED_COUNT);
+            continue;
+        }
         mine++;
         const int64_t g = I.base + p;
         P.code[g] = (uint8_t)code;
@@ -201,8 +210,10 @@ __device__ __forceinline__ void adj_point(const AdjParams &P, uint64_t it, bool 
         if (q[ax] < 0) continue;
         const int64_t gq = I.base + q[ax];
         atomicAdd(&P.acc[gq], (d[ax] / S) * lt);
+        // the last dependent of an upwind point in the system (fixed points
+        // never count down to zero)
         const uint32_t old = atomicSub(&P.cnt[gq], 1u);
-        if (old == 1u && P.code[gq] != 0) s_items[atomicAdd(s_n, 1u)] = ((uint64_t)j << 40) | (uint64_t)q[ax];
+        if (old == 1u) s_items[atomicAdd(s_n, 1u)] = ((uint64_t)j << 40) | (uint64_t)q[ax];
     }
 }
 
