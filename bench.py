@@ -25,11 +25,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid pts accepted/s @1024^3 FP64; batch vs serial; adjoint/forward time"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the restart driver per accepted point: read F once
-# (FP32, 4 B) and write T once (FP64, 8 B); the finalize kernel adds the
-# status byte (13 B for the whole solve).
-DRIVER_BYTES_PER_POINT_F32 = 12
+# Algorithmic bytes per accepted point of a whole solve: read F once, write T
+# once (FP64, 8 B) and the status byte once: 13 B with FP32 speeds, 17 B with
+# FP64 speeds.  The restart driver itself moves the first two (12 B / 16 B);
+# the finalize kernel writes the outputs.
+SOLVE_BYTES_PER_POINT = {torch.float32: 13, torch.float64: 17}
+DRIVER_BYTES_PER_POINT = {torch.float32: 12, torch.float64: 16}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "driver_traffic_random_speed_1024.txt")
+# the paper's restart strides (Sec. 5.1) plus the tuned range, in units of h
+PAPER_STRIDE_TABLE = "8:0.5,1.5,2,2.5,3.5,4,inf"
 
 
 def log(*a):
@@ -93,9 +97,69 @@ def kernel_tag():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(w, crop):
-    """Time the oracle (single thread, as it stands) on a crop of the speed field."""
+def host_info():
+    """CPU model, logical CPUs, the CPUs this process may use, and host RAM."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "mem_total_GiB": mem}
+
+
+class pinned_to_one_core:
+    """Run the calling thread on a single core (the first it may use), then
+    restore its affinity: the oracle is single-threaded and timed pinned."""
+
+    def __enter__(self):
+        self.saved = os.sched_getaffinity(0)
+        self.core = min(self.saved)
+        os.sched_setaffinity(0, {self.core})
+        return self
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.saved)
+
+
+def time_oracle(F, h, idx, val, width=math.inf, runs=5):
+    """The oracle as it stands (one thread, pinned to one core), ``runs``
+    times on the same inputs; init + heap + march timed, inputs prepared
+    outside.  Returns the median, mean and minimum seconds and the count of
+    accepted points."""
     import oracle
+    oracle._load()
+    secs, acc = [], None
+    with pinned_to_one_core() as pin:
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            T, st, stats, _ = oracle.solve(F, h, idx, val, width=width)
+            secs.append(time.perf_counter() - t0)
+            acc = int(stats.n_accepted)
+            del T, st
+    return {"runs": runs, "median_s": round(float(np.median(secs)), 4), "mean_s": round(float(np.mean(secs)), 4),
+            "min_s": round(float(np.min(secs)), 4), "accepted": acc,
+            "points_per_s": acc / float(np.median(secs)), "core": pin.core}
+
+
+def cpu_baseline(w, crop, small=None):
+    """The oracle on a bounded sample of the benchmark workload: the crop^3
+    block of the same FP32 speed field around source 0, one run, pinned to
+    one core.  ``small``: oracle 5-run medians of the point-source and
+    sphere workloads (see gpu_small_configs)."""
     F = w.F
     n = F.shape[0]
     src = [tuple(p) for p in w.meta["sources"]]
@@ -105,16 +169,60 @@ def cpu_baseline(w, crop):
               if all(c0[k] <= s[k] < c0[k] + crop for k in range(3))]
     idx = np.array([(a * crop + b) * crop + c for a, b, c in inside], dtype=np.int64)
     val = np.zeros(len(idx))
-    oracle._load()
-    t0 = time.perf_counter()
-    T, st, stats, _ = oracle.solve(sub, w.h, idx, val)
-    dt = time.perf_counter() - t0
-    return {"value": stats.n_accepted / dt, "unit": "grid points/s", "cores": 1, "kind": "oracle",
-            "seconds": round(dt, 3), "accepted": int(stats.n_accepted),
+    r = time_oracle(sub, w.h, idx, val, runs=1)
+    return {"value": r["points_per_s"], "unit": "grid points/s", "cores": 1, "kind": "oracle",
+            "seconds": r["median_s"], "accepted": r["accepted"],
             "sample": (f"oracle full-domain march on the {crop}^3 crop of the {n}^3 FP32 speed field "
                        f"at corner {tuple(c0)} with the {len(idx)} source(s) inside it, h = 1/{n - 1}, "
-                       "one thread, init + heap + march timed"),
-            "host": {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}}
+                       f"one thread pinned to core {r['core']}, init + heap + march timed, one run"),
+            "build": "gcc -O3 -ffp-contract=off -fno-fast-math (oracle/build.py)",
+            "host": host_info(), "configs": small}
+
+
+def gpu_small_configs(fmm, inputs, dev, steps, with_oracle=True):
+    """The point-source (64^3, F = 1 FP64, one source at the centre, full
+    march) and sphere-reinitialisation (256^3, 8 spheres, band 0.1, both
+    sides, FP64) workloads: GPU solve time (1 warm-up, then ``steps`` timed
+    solves; HIP events on the stream) at the paper's stride 2h and at 4h /
+    infinity, and the oracle's 5-run median on one pinned core."""
+    out = {}
+    for name, w, strides in (("point_source_64", inputs.point_source(64), (2.0, math.inf)),
+                             ("spheres_256", inputs.spheres(n=256), (2.0, 4.0))):
+        wd = w.to(dev)
+        T = torch.empty(w.shape, dtype=torch.float64, device=dev)
+        st = torch.empty(w.shape, dtype=torch.uint8, device=dev)
+        res = {"points": int(w.F.numel()), "seeds": int(w.seed_idx.numel()), "band_width": w.width}
+        stream = torch.cuda.current_stream()
+        for sh in strides:
+            sv = fmm.Solver(w.shape, w.seed_idx.numel(), w.h, band_width=w.width, stride=sh * w.h, timing=True,
+                            device=dev, speed_dtype=w.F.dtype)
+            sv.solve_into(wd.F, wd.seed_idx, wd.seed_val, T, st)
+            sv.stats()
+            ms, drv = [], []
+            for _ in range(max(steps, 5)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                sv.solve_into(wd.F, wd.seed_idx, wd.seed_val, T, st)
+                e1.record(stream)
+                s2 = sv.stats()
+                ms.append(e0.elapsed_time(e1))
+                drv.append(s2.ms_driver)
+            acc = int(s2.n_accepted)
+            res[f"gpu_{sh:g}h"] = {"ms_median": round(float(np.median(ms)), 4),
+                                   "ms_mean": round(float(np.mean(ms)), 4), "ms_min": round(float(np.min(ms)), 4),
+                                   "driver_ms_median": round(float(np.median(drv)), 4), "reps": len(ms),
+                                   "accepted": acc, "restarts": int(s2.n_restarts),
+                                   "points_per_s": acc / (float(np.median(ms)) / 1e3)}
+            log(f"  {name} stride {sh:g}h: median {np.median(ms):.3f} ms, {acc} accepted, "
+                f"{s2.n_restarts} restarts")
+            del sv
+        if with_oracle:
+            F, idx, val = w.numpy()
+            res["oracle"] = time_oracle(F, w.h, idx, val, width=w.width, runs=5)
+            log(f"  {name} oracle: median {res['oracle']['median_s']} s")
+        out[name] = res
+        del T, st, wd
+    return out
 
 
 def batch_vs_serial(fmm, inputs, dev, steps, tune=True):
@@ -244,36 +352,41 @@ def adjoint_vs_forward(fmm, inputs, dev, steps):
                       "stride 2h), adjoint = fmm_adjoint_batch of the 16 shots into one dL/dF"}
 
 
-def stride_table(fmm, w, spec, T, status):
+def stride_table(fmm, w, spec, T, status, inner_h=None, reps=2):
     """Driver time of the same solve for each (tile edge, restart stride) of
     ``spec`` ("edge:s1,s2,...;edge:..." with strides in units of h, 'inf'
-    allowed): two solves each, the minimum, with the solve statistics."""
+    allowed): ``reps`` solves each, the minimum, with the solve statistics
+    (local solves and reopened values per accepted point).  ``inner_h``: the
+    in-tile level step in units of h (None: the library default)."""
     out = {}
     for part in spec.split(";"):
         e_s, strides = part.split(":")
         e = int(e_s)
+        sv = fmm.Solver(w.shape, w.seed_idx.numel(), w.h, band_width=w.width, tile_edge=e, timing=True,
+                        time_limit_s=60, device=w.F.device, speed_dtype=w.F.dtype,
+                        inner_stride=None if inner_h is None else inner_h * w.h)
         for sh in (float(x) for x in strides.split(",")):
-            sv = fmm.Solver(w.shape, w.seed_idx.numel(), w.h, band_width=w.width, stride=sh * w.h,
-                            tile_edge=e, timing=True, time_limit_s=60, device=w.F.device,
-                            speed_dtype=w.F.dtype)
+            sv.opts.stride = sh * w.h
             best, st = None, None
-            key = f"E{e} {sh:g}h"
+            key = f"E{e} {sh:g}h" + ("" if inner_h is None else f" inner {inner_h:g}h")
             try:
-                for _ in range(2):
+                for _ in range(reps):
                     sv.solve_into(w.F, w.seed_idx, w.seed_val, T, status)
                     st = sv.stats()
                     best = st.ms_driver if best is None else min(best, st.ms_driver)
             except fmm.FmmError as ex:  # e.g. the 60 s time limit
                 out[key] = {"error": str(ex)}
                 log(f"  table {key}: {ex}")
-                del sv
                 continue
+            acc = max(1, st.n_accepted)
             out[key] = {"driver_ms": round(best, 2), "restarts": int(st.n_restarts),
                         "tile_marches": int(st.n_tile_marches),
-                        "solves_per_point": round(st.n_solves / st.n_accepted, 2)}
+                        "solves_per_point": round(st.n_solves / acc, 2),
+                        "reopened_per_point": round(st.n_reopened / acc, 2)}
             log(f"  table {key}: driver {best:.2f} ms, restarts {st.n_restarts}, "
-                f"marches {st.n_tile_marches}, solves/pt {st.n_solves / st.n_accepted:.2f}")
-            del sv
+                f"marches {st.n_tile_marches}, solves/pt {st.n_solves / acc:.2f}, "
+                f"reopened/pt {st.n_reopened / acc:.2f}")
+        del sv
     return out
 
 
@@ -292,9 +405,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-serial measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward measurement")
-    ap.add_argument("--table", default=None,
-                    help="also time a tile-edge x stride table on the same workload, e.g. "
-                         "'8:0.5,2,4,inf;4:2,4' (edge: strides in units of h); two solves each, minimum")
+    ap.add_argument("--table", default=PAPER_STRIDE_TABLE,
+                    help="tile-edge x stride table on the same workload, e.g. '8:0.5,2,4,inf;4:2,4' (edge: "
+                         "strides in units of h); two solves each, minimum; default: the paper's strides "
+                         "(Sec. 5.1) with 8^3 tiles; 'none' to skip")
+    ap.add_argument("--inner-table", default=None,
+                    help="in-tile level steps (units of h, comma separated, 'inf' allowed) to time at the "
+                         "chosen stride with the chosen tile edge, e.g. '0.25,0.5,1,inf'")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the 64^3 point-source and 256^3 sphere timings (GPU and oracle)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="GiB for a plain device copy, timed as achievable-HBM context and used to "
                          "calibrate HBM byte counters")
@@ -332,6 +451,8 @@ def main():
     w = inputs.random_speed(n=args.n, seed=args.seed, device=dev)
     torch.cuda.synchronize()
     log(f"  generated in {time.perf_counter() - t0:.1f}s; sources {w.meta['sources']}")
+    f_print = inputs.fingerprint(w.F)
+    log(f"  F {f_print}")
     N = w.F.numel()
     sweep = None
     stride_h = args.stride_h
@@ -378,23 +499,39 @@ def main():
     n_acc = int(stats.n_accepted)
     value = n_acc / (ms / 1e3)
     ms_drv = float(np.mean(drv))
-    bytes_per_pt = DRIVER_BYTES_PER_POINT_F32 if w.F.dtype == torch.float32 else 16
+    # the solve's algorithmic bytes (read F, write T and status once per
+    # accepted point), over the dominant kernel's duration and over the solve
+    bytes_per_pt = SOLVE_BYTES_PER_POINT[w.F.dtype]
     alg_bytes = bytes_per_pt * n_acc
     achieved = alg_bytes / (ms_drv / 1e3) / 1e9
+    drv_bytes = DRIVER_BYTES_PER_POINT[w.F.dtype] * n_acc
     tag = kernel_tag()
     traffic = read_traffic(tag, stride_h)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": "k_driver (restart loop: tile marches + exchange)",
                 "algorithmic_bytes_per_launch": alg_bytes, "bytes_per_accepted_point": bytes_per_pt,
-                "ms_per_launch": round(ms_drv, 4), "kernel_tag": tag}
+                "ms_per_launch": round(ms_drv, 4), "kernel_tag": tag,
+                "whole_solve": {"achieved": round(alg_bytes / (ms / 1e3) / 1e9, 2), "ms": round(ms, 4),
+                                "frac": round(alg_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5)},
+                "driver_own_bytes": {"bytes_per_accepted_point": DRIVER_BYTES_PER_POINT[w.F.dtype],
+                                     "achieved": round(drv_bytes / (ms_drv / 1e3) / 1e9, 2),
+                                     "frac": round(drv_bytes / (ms_drv / 1e3) / 1e9 / HBM_PEAK_GBS, 5)}}
     if traffic is not None:
         roofline["traffic_GBs"] = round(traffic / (ms_drv / 1e3) / 1e9, 2)
+        roofline["traffic_bytes_per_accepted_point"] = round(traffic / n_acc, 2)
 
     del solver
     table = None
-    if args.table:
+    if args.table and args.table != "none":
+        log("stride table ...")
         table = stride_table(fmm, w, args.table, T, status)
+    inner_table = None
+    if args.inner_table:
+        log("in-tile level-step table ...")
+        inner_table = {}
+        for ih in (float(x) for x in args.inner_table.split(",")):
+            inner_table.update(stride_table(fmm, w, f"{args.tile}:{stride_h:g}", T, status, inner_h=ih))
     del T, status
     torch.cuda.empty_cache()
     batch = None
@@ -412,10 +549,16 @@ def main():
         log(f"  forward {adj['forward_ms']} ms, adjoint {adj['adjoint_ms']} ms "
             f"({adj['adjoint_over_forward']}x), {adj['levels']} levels")
 
+    small = None
+    if not args.no_small:
+        log("64^3 point source and 256^3 spheres ...")
+        small = gpu_small_configs(fmm, inputs, dev, max(args.steps, 5), with_oracle=not args.no_cpu_baseline)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"timing the oracle on a {args.cpu_crop}^3 crop ...")
-        cpu = cpu_baseline(w, min(args.cpu_crop, args.n))
+        cpu = cpu_baseline(w, min(args.cpu_crop, args.n),
+                           {k: v.get("oracle") for k, v in small.items()} if small else None)
         log(f"  oracle {cpu['value']:.3e} points/s in {cpu['seconds']} s")
 
     out = {
@@ -436,13 +579,15 @@ def main():
                                "4 point sources",
                    "n": args.n, "h": w.h, "speed_dtype": "f32", "sources": len(w.meta["sources"]),
                    "band_width": "inf", "stride_h": stride_h, "stride_sweep_ms": sweep, "tile_edge": args.tile,
-                   "seed": args.seed,
+                   "seed": args.seed, "F_fingerprint": f_print,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_copy_probe": copy_probe,
         "batch_vs_serial": batch,
         "stride_table": table,
+        "inner_step_table": inner_table,
+        "small_configs": small,
         "adjoint_vs_forward": adj,
         "solve": {"accepted": n_acc, "points": N, "restarts": int(stats.n_restarts),
                   "tile_marches": int(stats.n_tile_marches), "solves": int(stats.n_solves),

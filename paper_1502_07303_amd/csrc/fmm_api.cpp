@@ -14,6 +14,7 @@
 
 using namespace fmm;
 
+
 namespace {
 
 int resolve_edge(const fmm_opts *o)
@@ -133,15 +134,69 @@ StageEvents *events_for(const void *ws, bool create)
     return &(g_events[ws] = e);
 }
 
+// Problem descriptor of q for tile edge E, its tiles numbered from `base`.
+Inst make_inst(const fmm_problem &q, int E, uint32_t base, const fmm_opts &o)
+{
+    Inst I;
+    memset(&I, 0, sizeof I);
+    int32_t t[3];
+    uint64_t nt = 0;
+    tile_grid(q.n0, q.n1, q.n2, E, t, &nt);
+    I.n0 = q.n0;
+    I.n1 = q.n1;
+    I.n2 = q.n2;
+    I.t0 = t[0];
+    I.t1 = t[1];
+    I.t2 = t[2];
+    I.base = base;
+    I.ntiles = (uint32_t)nt;
+    I.h = q.h;
+    I.stride = stride_of(o, q.h);
+    I.F = q.F;
+    I.T = q.T_out;
+    I.status = q.status_out;
+    I.seed_idx = q.n_seeds > 0 ? q.seed_idx : nullptr;
+    I.seed_val = q.n_seeds > 0 ? q.seed_val : nullptr;
+    I.n_seeds = q.n_seeds;
+    return I;
+}
+
+// Argument checks shared by every solve entry point.
+int check_solve_args(int64_t n, const fmm_problem *q, fmm_dtype F_dtype, const fmm_opts *opts)
+{
+    if (n <= 0 || n > MAX_PROBLEMS || !q) return FMM_EINVAL;
+    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return FMM_EINVAL;
+    if (!opts_ok(opts)) return FMM_EINVAL;
+    for (int64_t i = 0; i < n; i++)
+        if (!problem_ok(q[i])) return FMM_EINVAL;
+    return FMM_OK;
+}
+
+// The launch sequence of a solve: preparation (workspace reset, tiled
+// speeds, seeds), the restart driver, finalize; with stage events if `ev`.
+int enqueue_solve(const Params &P, const Inst *insts, int64_t n, int E, const fmm_opts &o, bool f64,
+                  StageEvents *ev, hipStream_t s)
+{
+    if (ev && hipEventRecord(ev->ev[0], s) != hipSuccess) return FMM_EHIP;
+    if (launch_prepare(P, insts, n, E, (o.flags & FMM_VALIDATE) != 0, f64, s) != hipSuccess) return FMM_EHIP;
+    if (ev && hipEventRecord(ev->ev[1], s) != hipSuccess) return FMM_EHIP;
+    uint32_t nwg = 0;
+    if (launch_driver(P, E, f64, s, &nwg) != hipSuccess) return FMM_EHIP;
+    if (ev && hipEventRecord(ev->ev[2], s) != hipSuccess) return FMM_EHIP;
+    if (launch_finalize(P, insts, n, E, s) != hipSuccess) return FMM_EHIP;
+    if (ev) {
+        if (hipEventRecord(ev->ev[3], s) != hipSuccess) return FMM_EHIP;
+        ev->valid = true;
+    }
+    return FMM_OK;
+}
+
 int run_batch(int64_t n, const fmm_problem *q, fmm_dtype F_dtype, const fmm_opts *opts, void *workspace,
               size_t workspace_bytes, void *stream)
 {
-    if (n <= 0 || n > MAX_PROBLEMS || !q || !workspace) return FMM_EINVAL;
-    if (F_dtype != FMM_F32 && F_dtype != FMM_F64) return FMM_EINVAL;
-    if (!opts_ok(opts)) return FMM_EINVAL;
-    if (((uintptr_t)workspace & 255u) != 0) return FMM_EINVAL;
-    for (int64_t i = 0; i < n; i++)
-        if (!problem_ok(q[i])) return FMM_EINVAL;
+    int rc = check_solve_args(n, q, F_dtype, opts);
+    if (rc != FMM_OK) return rc;
+    if (!workspace || ((uintptr_t)workspace & 255u) != 0) return FMM_EINVAL;
     fmm_opts o;
     if (opts)
         o = *opts;
@@ -155,31 +210,8 @@ int run_batch(int64_t n, const fmm_problem *q, fmm_dtype F_dtype, const fmm_opts
     if (workspace_bytes < L.total) return FMM_ENOMEM;
     Params P = make_params(L, workspace, o);
     std::vector<Inst> insts((size_t)n);
-    for (int64_t i = 0; i < n; i++) {
-        Inst &I = insts[(size_t)i];
-        memset(&I, 0, sizeof I);
-        int32_t t[3];
-        uint64_t nt = 0;
-        tile_grid(q[i].n0, q[i].n1, q[i].n2, E, t, &nt);
-        I.n0 = q[i].n0;
-        I.n1 = q[i].n1;
-        I.n2 = q[i].n2;
-        I.t0 = t[0];
-        I.t1 = t[1];
-        I.t2 = t[2];
-        I.base = bases[(size_t)i];
-        I.ntiles = (uint32_t)nt;
-        I.h = q[i].h;
-        I.stride = stride_of(o, q[i].h);
-        I.F = q[i].F;
-        I.T = q[i].T_out;
-        I.status = q[i].status_out;
-        I.seed_idx = q[i].n_seeds > 0 ? q[i].seed_idx : nullptr;
-        I.seed_val = q[i].n_seeds > 0 ? q[i].seed_val : nullptr;
-        I.n_seeds = q[i].n_seeds;
-    }
+    for (int64_t i = 0; i < n; i++) insts[(size_t)i] = make_inst(q[i], E, bases[(size_t)i], o);
     hipStream_t s = (hipStream_t)stream;
-    const bool f64 = F_dtype == FMM_F64;
     StageEvents *ev = nullptr;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return FMM_EHIP;
@@ -193,19 +225,7 @@ int run_batch(int64_t n, const fmm_problem *q, fmm_dtype F_dtype, const fmm_opts
         ev->valid = false;
         ev = nullptr;
     }
-    if (ev && hipEventRecord(ev->ev[0], s) != hipSuccess) return FMM_EHIP;
-    if (launch_prepare(P, insts.data(), n, E, (o.flags & FMM_VALIDATE) != 0, f64, s) != hipSuccess)
-        return FMM_EHIP;
-    if (ev && hipEventRecord(ev->ev[1], s) != hipSuccess) return FMM_EHIP;
-    uint32_t nwg = 0;
-    if (launch_driver(P, E, f64, s, &nwg) != hipSuccess) return FMM_EHIP;
-    if (ev && hipEventRecord(ev->ev[2], s) != hipSuccess) return FMM_EHIP;
-    if (launch_finalize(P, insts.data(), n, E, s) != hipSuccess) return FMM_EHIP;
-    if (ev) {
-        if (hipEventRecord(ev->ev[3], s) != hipSuccess) return FMM_EHIP;
-        ev->valid = true;
-    }
-    return FMM_OK;
+    return enqueue_solve(P, insts.data(), n, E, o, F_dtype == FMM_F64, ev, s);
 }
 
 // Statistics of problems [0, n) of the last solve in `workspace`.

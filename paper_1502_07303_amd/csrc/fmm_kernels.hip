@@ -678,16 +678,23 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 L.cf[(c0 * E + c1) * E + c2] = 1;
         }
     } else if (dbits) {
-        // interior cells next to a halo face whose values changed (Alg. 15)
+        // interior cells next to a halo source on a face whose values changed
+        // (Alg. 15's KNOWN_OLD values update their neighbours, Alg. 10).  Halo
+        // values above the starting level are not sources yet: the level loop
+        // marks their neighbours when it reaches them (mark_new_sources), and
+        // a band value never marks anything, so a cell gets a tentative value
+        // only from an accepted neighbour, as in the sequential march.
         for (int q = lane; q < 6 * FACE; q += 64) {
             const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
             if (!((dbits >> f) & 1u)) continue;
             int c0, c1, c2;
             face_cell<E>(f, u, w, c0, c1, c2);
-            const double vh = fabs(L.T[G::dom(c0, c1, c2)]);
+            const int dh = G::dom(c0, c1, c2);
+            if (!(L.fl[dh] & FL_SRC)) continue;
+            const double vh = fabs(L.T[dh]);
             face_inner<E>(f, c0, c1, c2);
             const int di = G::dom(c0, c1, c2);
-            if ((L.fl[di] & FL_UPD) && vh < FMM_INF && fabs(L.T[di]) > vh) L.cf[(c0 * E + c1) * E + c2] = 1;
+            if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > vh) L.cf[(c0 * E + c1) * E + c2] = 1;
         }
     }
     wave_sync();

@@ -150,6 +150,13 @@ def workspace_bytes(shape, n_seeds, opts: Optional[FmmOpts] = None, f_dtype=FMM_
                                                   ctypes.byref(opts) if opts else None))
 
 
+def _check_cuda(name: str, t: torch.Tensor, device) -> None:
+    """Every tensor handed to the library must live on the solve's GPU: a
+    host pointer reaching a kernel would fault instead of failing cleanly."""
+    if not t.is_cuda or t.device != device:
+        raise FmmError(FMM_EINVAL, f"{name} must be a CUDA tensor on {device} (got {t.device})")
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -206,6 +213,14 @@ class Solver:
                                    or not status.is_contiguous()):
             raise FmmError(FMM_EINVAL, "status must be a contiguous uint8 tensor of the solver's shape")
         ns = seed_idx.numel()
+        if ns:
+            _check_cuda("seed_idx", seed_idx, F.device)
+            _check_cuda("seed_val", seed_val, F.device)
+        _check_cuda("T", T, F.device)
+        if status is not None:
+            _check_cuda("status", status, F.device)
+        if self.ws.device != F.device:
+            raise FmmError(FMM_EINVAL, f"solver workspace is on {self.ws.device}, F on {F.device}")
         n0, n1, n2 = self.shape
         rc = self.lib.fmm_solve(n0, n1, n2, self.h, _ptr(F), dt, _ptr(seed_idx) if ns else None,
                                 _ptr(seed_val) if ns else None, ns, ctypes.byref(self.opts), _ptr(T),
@@ -291,6 +306,11 @@ class BatchSolver:
                 raise FmmError(FMM_EINVAL, f"problem {i}: seed_idx int64 and seed_val float64 of equal length")
             if not (idx.is_contiguous() and val.is_contiguous()):
                 raise FmmError(FMM_EINVAL, f"problem {i}: seed arrays must be contiguous")
+            if F.device != dev:
+                raise FmmError(FMM_EINVAL, f"problem {i}: F is on {F.device}, the batch on {dev}")
+            if idx.numel():
+                _check_cuda(f"problem {i}: seed_idx", idx, dev)
+                _check_cuda(f"problem {i}: seed_val", val, dev)
             if T_out is not None:
                 T = T_out[i]
                 if T.dtype != torch.float64 or T.shape != F.shape or not T.is_contiguous():
@@ -303,6 +323,9 @@ class BatchSolver:
                     raise FmmError(FMM_EINVAL, f"problem {i}: status_out must be contiguous uint8 of F's shape")
             else:
                 st = torch.empty(F.shape, dtype=torch.uint8, device=dev) if with_status else None
+            _check_cuda(f"problem {i}: T_out", T, dev)
+            if st is not None:
+                _check_cuda(f"problem {i}: status_out", st, dev)
             self.T.append(T)
             self.status.append(st)
             self.keep += [F, idx, val]
@@ -397,6 +420,9 @@ class AdjointSolver:
                                                f"tensor of shape {shape}")
             if F.dtype != dt or not F.is_contiguous() or F.dim() != 3:
                 raise FmmError(FMM_EINVAL, f"adjoint problem {i}: F must be contiguous 3-D of the batch dtype")
+            dev0 = problems[0]["F"].device
+            for name, t in (("F", F), ("T", T), ("status", st), ("dL_dT", gT), ("dL_dF", gF)):
+                _check_cuda(f"adjoint problem {i}: {name}", t, dev0)
             self.keep += [F, T, st, gT, gF]
             p = arr[i]
             p.n0, p.n1, p.n2 = shape

@@ -105,26 +105,53 @@ def gaussian_field(n: int, seed: int, corr_len: float = 0.05, device="cpu",
                    shape: Optional[tuple] = None) -> torch.Tensor:
     """Periodic Gaussian random field with unit variance and correlation
     exp(-r^2 / (2 l^2)), l = ``corr_len`` in unit-cube lengths (grid spacing
-    1/(n-1)).  White noise from a seeded torch generator on ``device`` is
-    filtered in Fourier space by exp(-|k|^2 l^2 / 4), then normalised."""
-    shape = shape or (n, n, n)
+    1/(n-1)); returned in FP64.
+
+    White noise (FP32 normals from a seeded torch generator on ``device``) is
+    convolved, one axis after the other and periodically, with a Gaussian
+    kernel of standard deviation l / sqrt(2) truncated at 4 standard
+    deviations (the convolution of two such kernels gives the correlation
+    above), then shifted and scaled to zero mean and unit variance.  Every
+    step is an elementwise FP64 operation in a fixed order, so the same seed,
+    shape and device give the same bits on every run (no FFT library whose
+    kernel choice could change between runs)."""
+    shape = tuple(shape or (n, n, n))
     h = 1.0 / (n - 1)
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
-    w = torch.randn(shape, generator=gen, device=device, dtype=torch.float32)
-    W = torch.fft.rfftn(w)
-    del w
-    k = [2 * math.pi * torch.fft.fftfreq(m, d=h, device=device) for m in shape[:2]]
-    k.append(2 * math.pi * torch.fft.rfftfreq(shape[2], d=h, device=device))
-    a = [torch.exp(-(kk ** 2) * corr_len ** 2 / 4).to(torch.float32) for kk in k]
-    W *= a[0][:, None, None]
-    W *= a[1][None, :, None]
-    W *= a[2][None, None, :]
-    g = torch.fft.irfftn(W, s=shape)
-    del W
+    g = torch.randn(shape, generator=gen, device=device, dtype=torch.float32).to(torch.float64)
+    s = corr_len / math.sqrt(2.0) / h  # kernel standard deviation in grid spacings
+    R = max(1, int(math.ceil(4.0 * s)))
+    taps = [math.exp(-0.5 * (j / s) ** 2) for j in range(-R, R + 1)]
+    tot = math.fsum(taps)
+    taps = [t / tot for t in taps]
+    for ax in range(3):
+        m = shape[ax]
+        # periodic extension by R on both sides (tiled as often as needed)
+        reps = (R + m - 1) // m
+        ext = torch.cat([g] * (2 * reps + 1), dim=ax)
+        P = ext.narrow(ax, reps * m - R, m + 2 * R)
+        del ext
+        out = torch.zeros_like(g)
+        for j, wj in enumerate(taps):
+            out.add_(P.narrow(ax, j, m), alpha=wj)
+        del P
+        g = out
     g -= g.mean()
     g /= g.std()
     return g
+
+
+def fingerprint(t: torch.Tensor) -> str:
+    """CRC-32 of a tensor's bytes (copied to the host in chunks), to tie a
+    measurement to the exact input it ran on."""
+    import zlib
+    flat = t.detach().contiguous().reshape(-1)
+    crc = 0
+    step = 1 << 26
+    for a in range(0, flat.numel(), step):
+        crc = zlib.crc32(flat[a:a + step].cpu().numpy().tobytes(), crc)
+    return f"crc32:{crc:08x}"
 
 
 def random_speed(n: int = 1024, n_sources: int = 4, seed: int = 0, corr_len: float = 0.05,

@@ -231,3 +231,22 @@ def test_adjoint_workspace_and_rejects(fmm):
         setattr(bad[0], field, val)
         assert lib.fmm_adjoint_batch(1, bad, fmm.FMM_F64, ws, 1 << 30, None) == fmm.FMM_EINVAL, field
     assert lib.fmm_adjoint_batch(1, good, 5, ws, 1 << 30, None) == fmm.FMM_EINVAL
+
+
+def test_binding_rejects_host_tensors(fmm):
+    """Tensors on the host never reach the library: the binding raises
+    FMM_EINVAL before any launch (a host pointer in a kernel would fault)."""
+    import torch
+    F = torch.ones((8, 8, 8), dtype=torch.float64)
+    idx = torch.zeros(1, dtype=torch.int64)
+    val = torch.zeros(1, dtype=torch.float64)
+    T = torch.empty((8, 8, 8), dtype=torch.float64)
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.BatchSolver([{"F": F, "h": 0.1, "seed_idx": idx, "seed_val": val}])
+    assert ei.value.code == fmm.FMM_EINVAL
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.AdjointSolver([{"F": F, "h": 0.1, "T": T, "status": torch.zeros((8, 8, 8), dtype=torch.uint8),
+                            "dL_dT": T, "dL_dF": T}])
+    assert ei.value.code == fmm.FMM_EINVAL
+    with pytest.raises(fmm.FmmError):
+        fmm._check_cuda("seed_idx", idx, torch.device("cuda:0"))

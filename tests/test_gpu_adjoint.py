@@ -200,36 +200,46 @@ def test_finite_differences_tomography_256(fmm):
             Tv, _ = forward(Fv)
             return float(((Tv.reshape(16, -1)[:, rec] - dobs) ** 2).sum().item())
 
+    # Cells: 20 random ones among the 400 with the largest |dL/dF| (the
+    # gradient is concentrated next to the shots).  Far below those the loss's
+    # own run-to-run jitter (a travel time carries a few ulps that depend on
+    # the order in which tiles were claimed; about 1e-9 in a step-1e-6
+    # difference) is no longer small against the difference: the jitter is
+    # absolute, so the relative noise grows as |dL/dF| falls.  A cell whose
+    # one-sided slopes disagree by more than 1e-4 lies on a kink of the
+    # solution map within the step and is skipped (counted).
     rng = np.random.default_rng(3)
-    big = np.flatnonzero(np.abs(g) > 1e-2 * np.abs(g).max())
-    cells = rng.choice(big, size=20, replace=False)
+    big = np.argsort(-np.abs(g))[:400]
+    print(f"candidate cells: |dL/dF| from {np.abs(g[big]).min():.3e} to {np.abs(g[big]).max():.3e}", flush=True)
+    order = rng.permutation(big)
     base = tp["F"]
-    used, worst6, worst5 = 0, 0.0, 0.0
-    for c in cells:
+    used, skipped, worst6, worst5 = 0, 0, 0.0, 0.0
+    for c in order:
+        if used == 20:
+            break
         L = {}
         for s in (-1e-5, -1e-6, 0.0, 1e-6, 1e-5):
             Fp = base.clone()
             Fp.view(-1)[int(c)] += s
             L[s] = loss_at(Fp)
-        # step 1e-6: the central difference, and the one-sided slopes whose
-        # disagreement bounds its rounding noise (and flags a kink)
         e = 1e-6
         back, fwd = (L[0.0] - L[-e]) / e, (L[e] - L[0.0]) / e
         c6 = (L[e] - L[-e]) / (2 * e)
         if abs(fwd - back) > 1e-4 * abs(c6):
-            continue  # a kink of the solution map within the step
+            skipped += 1
+            print(f"  cell {int(c)}: skipped (one-sided slopes differ by {abs(fwd - back) / abs(c6):.1e})",
+                  flush=True)
+            continue
         c5 = (L[1e-5] - L[-1e-5]) / 2e-5
         used += 1
         err6 = abs(g[c] - c6) / abs(c6)
         err5 = abs(g[c] - c5) / abs(c5)
-        print(f"  cell {int(c)}: adjoint {g[c]:.12e} fd(1e-6) {c6:.12e} rel {err6:.2e} (noise "
+        print(f"  cell {int(c)}: adjoint {g[c]:.12e} fd(1e-6) {c6:.12e} rel {err6:.2e} (one-sided spread "
               f"{abs(fwd - back) / abs(c6):.1e}) fd(1e-5) rel {err5:.2e}", flush=True)
-        # step 1e-5 carries ten times less rounding noise: the strict bar; at
-        # step 1e-6 the bar is widened by that difference's own disagreement
-        # with the step-1e-5 one
-        assert err5 <= 1e-6, c
-        assert err6 <= 1e-6 + abs(c6 - c5) / abs(c6), c
+        assert err6 <= 1e-6, (int(c), err6)
+        assert err5 <= 1e-6, (int(c), err5)
         worst6, worst5 = max(worst6, err6), max(worst5, err5)
-    print(f"tomography FD: {used} cells, worst relative error {worst6:.3e} (step 1e-6), "
-          f"{worst5:.3e} (step 1e-5)", flush=True)
-    assert used >= 15
+    print(f"tomography FD: {used} cells used, {skipped} skipped at kinks, {len(big)} candidates; worst relative "
+          f"error {worst6:.3e} (step 1e-6), {worst5:.3e} (step 1e-5)", flush=True)
+    assert used == 20
+    assert skipped <= 10

@@ -39,7 +39,7 @@ def test_paper_case_parity(fmm, oracle_mod, case):
     w = inputs.paper_case(case, n=48)
     F, idx, val = w.numpy()
     To, so, sto, _ = oracle_mod.solve(F, w.h, idx, val)
-    for stride_h in (0.5, 2.0, math.inf):
+    for stride_h in (0.5, 2.0, 4.0, math.inf):
         Tg, sg, st = gpu(fmm, w, stride=stride_h * w.h)
         rep = parity_report(Tg, sg, To, so)
         assert rep["same_status"], (stride_h, rep)

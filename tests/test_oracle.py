@@ -78,6 +78,35 @@ def test_g_against_exact_bisection(oracle_mod):
     assert worst <= 2.0, worst
 
 
+def test_g_batch_is_the_pinned_g(oracle_mod):
+    """The batch form (what the device solver is compared with bit for bit)
+    returns exactly the scalar G on arguments drawn like the device test's
+    (absent axes, ties), and those values lie within 2 ulp of the exact root
+    of sum max(u - a_i, 0)^2 = r^2 (exact rationals), so the batch is pinned
+    to the equation, not to itself."""
+    import numpy as np
+    rng = np.random.default_rng(11)
+    n = 3000
+    r = rng.uniform(1e-4, 1.0, size=n)
+    base = rng.uniform(0, 50, size=(n, 1))
+    a = base + rng.uniform(0, 1.5, size=(n, 3)) * r[:, None]
+    a[rng.random(n) < 0.2, 2] = INF
+    a[rng.random(n) < 0.1, 1] = INF
+    tie = rng.random(n) < 0.1
+    a[tie, 1] = a[tie, 0]
+    a[:5] = INF  # no upwind value at all
+    got = oracle_mod.godunov_batch(a, r)
+    scalar = np.array([oracle_mod.godunov(a[i, 0], a[i, 1], a[i, 2], r[i]) for i in range(n)])
+    assert np.array_equal(got.view(np.uint64), scalar.view(np.uint64))
+    assert np.all(np.isinf(got[:5]))
+    worst = 0.0
+    for i in range(5, n, 6):
+        lo, hi = exact_root_bracket(list(a[i]), float(r[i]))
+        fg = Fraction(float(got[i]))
+        worst = max(worst, max(float(lo - fg), float(fg - hi), 0.0) / math.ulp(float(got[i])))
+    assert worst <= 2.0, worst
+
+
 def test_g_symmetric_and_bounded(oracle_mod):
     rng = random.Random(4)
     import itertools
