@@ -159,6 +159,37 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
  * are host-side objects the library keeps per workspace address. */
 int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * fmm_solve_noalloc() is fmm_solve() without the workspace arguments.  Its
+ * workspace is a fixed device array of FMM_NOALLOC_MAX_BYTES bytes inside the
+ * library: every GPU the library's code is loaded onto holds one copy until
+ * the process ends.  The call allocates nothing (no hipMalloc, no host
+ * containers, no events); the caller passes inputs and outputs as for
+ * fmm_solve().
+ *   - A problem whose fmm_workspace_bytes() exceeds FMM_NOALLOC_MAX_BYTES is
+ *     rejected with FMM_ENOMEM before anything is enqueued: with 8^3 tiles
+ *     the largest cubes that fit are 160^3 (FP32 speeds, about 14.4 bytes
+ *     per point) and 152^3 (FP64 speeds, about 18.4 bytes per point).
+ *   - error_out (device pointer, may be NULL) receives, in stream order after
+ *     the solve, the FMM_DERR_* bits of this solve (0 when it succeeded).
+ *     fmm_get_stats() does not apply to this entry point.
+ *   - FMM_TIMING is ignored.
+ *   - All calls on one GPU share that GPU's array and it keeps the last
+ *     call's contents (each solve resets what it reads).  Calls that overlap
+ *     in time on one GPU (different streams, different host threads) race
+ *     and give undefined results: the caller must order them, e.g. on one
+ *     stream.
+ * Returns the host-detectable codes of fmm_solve() (FMM_EINVAL, FMM_ENOMEM,
+ * FMM_EHIP) or FMM_OK once the work is enqueued.
+ * ------------------------------------------------------------------------ */
+#define FMM_NOALLOC_MAX_BYTES (64u << 20)
+int fmm_solve_noalloc(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_dtype F_dtype,
+                      const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, const fmm_opts *opts,
+                      double *T_out, uint8_t *status_out, uint32_t *error_out, void *stream);
+
 /* The local solver on the device (Alg. 11, Eqs. 2-7): out[i] = G(a[3i],
  * a[3i+1], a[3i+2], r[i]) for i < n, where a holds per-axis upwind values
  * (+INFINITY for an axis without one) and r = h / F.  All device pointers. */

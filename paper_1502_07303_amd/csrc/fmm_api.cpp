@@ -14,6 +14,34 @@
 
 using namespace fmm;
 
+// Workspace of fmm_solve_noalloc(): a fixed device array, one copy per GPU,
+// reserved when the library's code object is loaded onto that GPU.  In host
+// code `scratch` names a host-side stand-in, not device memory: kernels and
+// copies get the device address that hipGetSymbolAddress() returns for the
+// current device, looked up once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[FMM_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of the current device's scratch array (nullptr on failure).
+void *scratch_for_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -326,6 +354,46 @@ int fmm_solve(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_d
     q.T_out = T_out;
     q.status_out = status_out;
     return run_batch(1, &q, F_dtype, opts, workspace, workspace_bytes, stream);
+}
+
+int fmm_solve_noalloc(int64_t n0, int64_t n1, int64_t n2, double h, const void *F, fmm_dtype F_dtype,
+                      const int64_t *seed_idx, const double *seed_val, int64_t n_seeds, const fmm_opts *opts,
+                      double *T_out, uint8_t *status_out, uint32_t *error_out, void *stream)
+{
+    fmm_problem q;
+    q.n0 = n0;
+    q.n1 = n1;
+    q.n2 = n2;
+    q.h = h;
+    q.F = F;
+    q.seed_idx = seed_idx;
+    q.seed_val = seed_val;
+    q.n_seeds = n_seeds;
+    q.T_out = T_out;
+    q.status_out = status_out;
+    int rc = check_solve_args(1, &q, F_dtype, opts);
+    if (rc != FMM_OK) return rc;
+    fmm_opts o;
+    if (opts)
+        o = *opts;
+    else
+        fmm_default_opts(&o);
+    o.flags &= ~(uint32_t)FMM_TIMING;  // no stage events: creating them allocates
+    const int E = resolve_edge(&o);
+    Layout L;
+    uint32_t base = 0;
+    const int64_t dims[3] = {n0, n1, n2};
+    if (!make_layout(1, dims, E, F_dtype == FMM_F64 ? 8 : 4, &L, &base)) return FMM_EINVAL;
+    if (L.total > (size_t)FMM_NOALLOC_MAX_BYTES) return FMM_ENOMEM;
+    void *ws = scratch_for_current_device();
+    if (!ws) return FMM_EHIP;
+    const Params P = make_params(L, ws, o);
+    const Inst I = make_inst(q, E, base, o);
+    hipStream_t s = (hipStream_t)stream;
+    rc = enqueue_solve(P, &I, 1, E, o, F_dtype == FMM_F64, nullptr, s);
+    if (rc != FMM_OK) return rc;
+    if (error_out && launch_report_error(P, error_out, s) != hipSuccess) return FMM_EHIP;
+    return FMM_OK;
 }
 
 int fmm_get_stats(const void *workspace, fmm_stats *out, void *stream)

@@ -224,5 +224,6 @@ hipError_t launch_prepare(const Params &P, const Inst *insts, int64_t n, int E, 
 hipError_t launch_driver(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out);
 hipError_t launch_finalize(const Params &P, const Inst *insts, int64_t n, int E, hipStream_t s);
 hipError_t launch_eval_godunov(const double *a, const double *r, double *out, int64_t n, hipStream_t s);
+hipError_t launch_report_error(const Params &P, uint32_t *out, hipStream_t s);
 
 }  // namespace fmm

@@ -1633,6 +1633,19 @@ hipError_t launch_finalize(const Params &P, const Inst *insts, int64_t n, int E,
     }
 }
 
+// The device error bits of the last solve (input errors found before the
+// driver and errors raised while it ran) copied to a caller's word.
+__global__ void k_report_error(const Ctrl *c, uint32_t *out)
+{
+    if (threadIdx.x == 0) *out = c->error | c->error_run;
+}
+
+hipError_t launch_report_error(const Params &P, uint32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_report_error, dim3(1), dim3(64), 0, s, (const Ctrl *)P.ctrl, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_eval_godunov(const double *a, const double *r, double *out, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

@@ -93,6 +93,9 @@ def load_library(path: str = LIB_PATH):
     lib.fmm_solve.restype = ctypes.c_int
     lib.fmm_get_stats.argtypes = [P, ctypes.POINTER(FmmStats), P]
     lib.fmm_get_stats.restype = ctypes.c_int
+    lib.fmm_solve_noalloc.argtypes = [i64, i64, i64, dbl, P, ctypes.c_int, P, P, i64, ctypes.POINTER(FmmOpts),
+                                      P, P, P, P]
+    lib.fmm_solve_noalloc.restype = ctypes.c_int
     lib.fmm_eval_godunov.argtypes = [P, P, P, i64, P]
     lib.fmm_eval_godunov.restype = ctypes.c_int
     PP = ctypes.POINTER(FmmProblem)
@@ -250,6 +253,50 @@ def solve(F: torch.Tensor, h: float, seed_idx: torch.Tensor, seed_val: torch.Ten
     s.solve_into(F, seed_idx, seed_val, T, status)
     st = s.stats(check=check)
     return T, status, st
+
+
+NOALLOC_MAX_BYTES = 64 << 20  # FMM_NOALLOC_MAX_BYTES
+
+
+def solve_noalloc_into(F: torch.Tensor, h: float, seed_idx: torch.Tensor, seed_val: torch.Tensor, T: torch.Tensor,
+                       status: Optional[torch.Tensor] = None, error: Optional[torch.Tensor] = None,
+                       opts: Optional[FmmOpts] = None, stream=None) -> None:
+    """Enqueue fmm_solve_noalloc(): a solve whose workspace is the library's
+    fixed per-GPU array (nothing is allocated).  ``error`` (a 1-element uint32
+    CUDA tensor, optional) receives the device error bits in stream order.
+    Calls that overlap on one GPU race; order them on one stream."""
+    dev = F.device
+    _check_cuda("F", F, dev)
+    dt = _dtype_code(F.dtype)
+    shape = tuple(F.shape)
+    if F.dim() != 3 or not F.is_contiguous():
+        raise FmmError(FMM_EINVAL, "F must be a contiguous 3-D CUDA tensor")
+    if seed_idx.dtype != torch.int64 or seed_val.dtype != torch.float64 or seed_idx.numel() != seed_val.numel():
+        raise FmmError(FMM_EINVAL, "seed_idx must be int64 and seed_val float64, of equal length")
+    if not (seed_idx.is_contiguous() and seed_val.is_contiguous()):
+        raise FmmError(FMM_EINVAL, "seed arrays must be contiguous")
+    ns = seed_idx.numel()
+    if ns:
+        _check_cuda("seed_idx", seed_idx, dev)
+        _check_cuda("seed_val", seed_val, dev)
+    if T.dtype != torch.float64 or tuple(T.shape) != shape or not T.is_contiguous():
+        raise FmmError(FMM_EINVAL, "T must be a contiguous float64 tensor of F's shape")
+    _check_cuda("T", T, dev)
+    if status is not None:
+        if status.dtype != torch.uint8 or tuple(status.shape) != shape or not status.is_contiguous():
+            raise FmmError(FMM_EINVAL, "status must be a contiguous uint8 tensor of F's shape")
+        _check_cuda("status", status, dev)
+    if error is not None:
+        if error.dtype not in (torch.int32, torch.uint32) or error.numel() < 1 or not error.is_contiguous():
+            raise FmmError(FMM_EINVAL, "error must be a contiguous 32-bit integer tensor")
+        _check_cuda("error", error, dev)
+    o = opts if opts is not None else make_opts()
+    n0, n1, n2 = shape
+    rc = load_library().fmm_solve_noalloc(n0, n1, n2, float(h), _ptr(F), dt, _ptr(seed_idx) if ns else None,
+                                          _ptr(seed_val) if ns else None, ns, ctypes.byref(o), _ptr(T),
+                                          _ptr(status), _ptr(error), _stream_handle(stream))
+    if rc != FMM_OK:
+        raise FmmError(rc, f"fmm_solve_noalloc: {strerror(rc)}")
 
 
 def eval_godunov(a: torch.Tensor, r: torch.Tensor) -> torch.Tensor:

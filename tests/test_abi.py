@@ -233,6 +233,41 @@ def test_adjoint_workspace_and_rejects(fmm):
     assert lib.fmm_adjoint_batch(1, good, 5, ws, 1 << 30, None) == fmm.FMM_EINVAL
 
 
+# --------------------------------------------------------------------------
+# the entry point that allocates nothing (host side)
+
+def _call_noalloc(fmm, **kw):
+    lib = fmm.load_library()
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: host validation fails first
+    args = dict(n0=8, n1=8, n2=8, h=0.1, F=fake, dt=fmm.FMM_F64, idx=fake, val=fake, ns=1, opts=None,
+                T=fake, st=None, err=None, stream=None)
+    args.update(kw)
+    o = args["opts"]
+    return lib.fmm_solve_noalloc(args["n0"], args["n1"], args["n2"], args["h"], args["F"], args["dt"],
+                                 args["idx"], args["val"], args["ns"], ctypes.byref(o) if o is not None else None,
+                                 args["T"], args["st"], args["err"], args["stream"])
+
+
+@pytest.mark.parametrize("kw", [{"n0": 0}, {"h": 0.0}, {"F": None}, {"T": None}, {"dt": 3}, {"ns": -1},
+                                {"idx": None}])
+def test_noalloc_rejects_bad_arguments(fmm, kw):
+    assert _call_noalloc(fmm, **kw) == fmm.FMM_EINVAL
+
+
+def test_noalloc_rejects_grids_beyond_its_array(fmm):
+    """Grids whose workspace exceeds the fixed array are refused on the host
+    (FMM_ENOMEM) before anything is enqueued; the limit is the header's."""
+    lib = fmm.load_library()
+    limit = fmm.NOALLOC_MAX_BYTES
+    text = open(HEADER).read()
+    assert re.search(r"#define FMM_NOALLOC_MAX_BYTES \(64u << 20\)", text)
+    for n, dt in ((161, fmm.FMM_F32), (153, fmm.FMM_F64), (1024, fmm.FMM_F32)):
+        assert lib.fmm_workspace_bytes(n, n, n, 1, dt, None) > limit
+        assert _call_noalloc(fmm, n0=n, n1=n, n2=n, dt=dt) == fmm.FMM_ENOMEM
+    for n, dt in ((160, fmm.FMM_F32), (152, fmm.FMM_F64)):
+        assert lib.fmm_workspace_bytes(n, n, n, 1, dt, None) <= limit
+
+
 def test_binding_rejects_host_tensors(fmm):
     """Tensors on the host never reach the library: the binding raises
     FMM_EINVAL before any launch (a host pointer in a kernel would fault)."""
@@ -241,6 +276,9 @@ def test_binding_rejects_host_tensors(fmm):
     idx = torch.zeros(1, dtype=torch.int64)
     val = torch.zeros(1, dtype=torch.float64)
     T = torch.empty((8, 8, 8), dtype=torch.float64)
+    with pytest.raises(fmm.FmmError) as ei:
+        fmm.solve_noalloc_into(F, 0.1, idx, val, T)
+    assert ei.value.code == fmm.FMM_EINVAL
     with pytest.raises(fmm.FmmError) as ei:
         fmm.BatchSolver([{"F": F, "h": 0.1, "seed_idx": idx, "seed_val": val}])
     assert ei.value.code == fmm.FMM_EINVAL
