@@ -42,18 +42,38 @@ __global__ void k_eval_godunov(const double *__restrict__ a, const double *__res
 }
 
 // ---------------------------------------------------------------------------
-// Tile geometry and per-wavefront LDS.
+// Tile geometry, thread groups and per-tile LDS.
 
 template <int E> struct Geo {
     static constexpr int D = E + 2;          // tile plus one-point halo per side
     static constexpr int DV = D * D * D;
     static constexpr int V = E * E * E;      // interior points
-    static constexpr int K = (V + 63) / 64;  // interior points per lane in a scan
+    static constexpr int K = (V + 63) / 64;  // interior points per lane in a one-wavefront scan
     static constexpr int FACE = E * E;
     static constexpr int OX = D * D, OY = D, OZ = 1;
     static constexpr int LOG = (E == 4) ? 2 : (E == 8) ? 3 : 4;
     __device__ static constexpr int dom(int i0, int i1, int i2) { return ((i0 + 1) * D + (i1 + 1)) * D + (i2 + 1); }
     __device__ static constexpr int domp(int p) { return dom(p >> (2 * LOG), (p >> LOG) & (E - 1), p & (E - 1)); }
+};
+
+// A tile is marched by a group of G threads: one wavefront (G = 64) for the
+// 4^3 and 8^3 tiles, several per workgroup; the whole workgroup of G / 64
+// wavefronts for a 16^3 tile, so that a front crossing the tile is handed
+// from cell to cell in LDS instead of across tile faces through HBM.
+template <int G> struct Grp {
+    static constexpr int NWV = G / 64;  // wavefronts in the group
+    __device__ static __forceinline__ int rank() { return G == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x; }
+    __device__ static __forceinline__ int wave()
+    {
+        return G == 64 ? 0 : (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    }
+    __device__ static __forceinline__ void sync()
+    {
+        if constexpr (G == 64)
+            wave_sync();
+        else
+            __syncthreads();
+    }
 };
 
 // Coordinates of halo cell (face f, in-face position u, w): face f = 2*axis +
@@ -86,7 +106,7 @@ template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int 
 #define FMM_E8_WAVES_F64 10
 #endif
 
-constexpr int STAGE = 64;  // staged list appends per wavefront before a flush
+constexpr int STAGE = 64;  // staged list appends per group before a flush
 constexpr int MAX_ROUNDS = 1 << 16;
 
 // Cell flags.  FL_SRC caches "is a source at the current level" (a seed, or a
@@ -96,15 +116,26 @@ constexpr int MAX_ROUNDS = 1 << 16;
 enum : uint8_t { FL_SEED = 1, FL_UPD = 2, FL_CHG = 4, FL_SRC = 8 };
 enum { MODE_INIT = 0, MODE_M1 = 1, MODE_M2 = 2 };
 
-template <int E, typename FT> struct WaveLds {
-    double T[Geo<E>::DV];                 // domain values (interior + face halos)
-    FT F[Geo<E>::V];                      // interior speeds (FP32), or h / F (FP64)
-    uint16_t list[Geo<E>::V];             // candidate list (interior indices)
-    alignas(8) uint8_t cf[Geo<E>::V + 8]; // candidate flags (interior indices); cf[V] takes unwanted marks
-    uint8_t fl[Geo<E>::DV];               // FL_* per domain cell
-    uint32_t stL[STAGE];                  // staged live-list appends
-    uint32_t stD[STAGE];                  // staged dirty-list appends
-    unsigned long long bm[12];            // per face and side: smallest changed band value
+// LDS of one tile march.  Candidate flags are bytes for a one-wavefront group
+// (compacted eight at a time) and bits for a workgroup (a 16^3 tile's bytes
+// would not leave room for two tiles per CU).
+template <int E, typename FT, int G> struct TileLds {
+    static constexpr bool BITS = G > 64;
+    static constexpr int NWV = G / 64;
+    double T[Geo<E>::DV];                                // domain values (interior + face halos)
+    FT F[Geo<E>::V];                                     // interior speeds (FP32), or h / F (FP64)
+    uint16_t list[Geo<E>::V];                            // candidate list (interior indices)
+    alignas(8) uint8_t cf[BITS ? 8 : Geo<E>::V];         // byte flags
+    uint32_t cfw[BITS ? Geo<E>::V / 32 : 1];             // bit flags
+    uint8_t fl[Geo<E>::DV];                              // FL_* per domain cell
+    uint32_t stL[STAGE];                                 // staged live-list appends
+    uint32_t stD[STAGE];                                 // staged dirty-list appends
+    unsigned long long bm[12];                           // per face and side: smallest changed band value
+    // group scratch (G > 64): per-wavefront candidate counts and partial
+    // reductions, and broadcast words
+    uint32_t gcnt[NWV], gu[NWV];
+    double gd0[NWV], gd1[NWV];
+    uint32_t bc[8];
 };
 
 constexpr uint32_t NO_INST = 0xFFFFFFFFu;
@@ -128,13 +159,88 @@ struct WaveState {
 #ifdef FMM_PROFILE
     unsigned long long prof[16];
 #endif
-    uint32_t nL, nD;      // staged entries (wave-uniform)
+    uint32_t nL, nD;      // staged entries (group-uniform; kept by the group's first wavefront)
     uint32_t acc;         // problem the three accumulators below belong to (NO_INST: none)
-    uint32_t pending;     // tiles newly dirtied for the next restart
+    uint32_t pending;     // tiles newly dirtied for the next restart (first wavefront of the group)
     double gmin0, gmin1;  // running min of band minima
-    unsigned long long n_march, n_round;  // wave-uniform counters
+    unsigned long long n_march, n_round;  // group-uniform counters (first wavefront of the group)
     unsigned long long n_solve, n_reopen;  // per-lane counters
 };
+
+// ---------------------------------------------------------------------------
+// Group reductions and broadcasts.  For G > 64 every value that steers
+// control flow must be the same in all wavefronts of the group, so values
+// read from memory that other workgroups may be changing are read by one
+// thread and broadcast through LDS.
+
+template <int E, typename FT, int G>
+__device__ __forceinline__ bool grp_any(TileLds<E, FT, G> &L, bool b)
+{
+    const bool w = __ballot(b) != 0ull;
+    if constexpr (G == 64) {
+        return w;
+    } else {
+        if ((threadIdx.x & 63) == 0) L.gu[Grp<G>::wave()] = w ? 1u : 0u;
+        __syncthreads();
+        uint32_t r = 0;
+#pragma unroll
+        for (int k = 0; k < G / 64; k++) r |= L.gu[k];
+        __syncthreads();
+        return r != 0;
+    }
+}
+
+template <int E, typename FT, int G>
+__device__ __forceinline__ uint32_t grp_or(TileLds<E, FT, G> &L, uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    if constexpr (G == 64) {
+        return v;
+    } else {
+        if ((threadIdx.x & 63) == 0) L.gu[Grp<G>::wave()] = v;
+        __syncthreads();
+        uint32_t r = 0;
+#pragma unroll
+        for (int k = 0; k < G / 64; k++) r |= L.gu[k];
+        __syncthreads();
+        return r;
+    }
+}
+
+template <int E, typename FT, int G>
+__device__ __forceinline__ void grp_min2(TileLds<E, FT, G> &L, double &a, double &b)
+{
+    a = wave_min(a);
+    b = wave_min(b);
+    if constexpr (G > 64) {
+        if ((threadIdx.x & 63) == 0) {
+            L.gd0[Grp<G>::wave()] = a;
+            L.gd1[Grp<G>::wave()] = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < G / 64; k++) {
+            a = fmin(a, L.gd0[k]);
+            b = fmin(b, L.gd1[k]);
+        }
+        __syncthreads();
+    }
+}
+
+// Broadcast a value held by rank 0 of the group to all of it.
+template <int E, typename FT, int G>
+__device__ __forceinline__ uint32_t grp_bcast(TileLds<E, FT, G> &L, uint32_t v)
+{
+    if constexpr (G == 64) {
+        return bcast0(v);
+    } else {
+        if (threadIdx.x == 0) L.bc[0] = v;
+        __syncthreads();
+        const uint32_t r = L.bc[0];
+        __syncthreads();
+        return r;
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Device-wide barrier for the persistent driver.  All workgroups of the
@@ -147,7 +253,7 @@ __device__ bool grid_barrier(Ctrl *c, uint32_t &gen, uint32_t nwg, uint32_t *s_o
 }
 
 // ---------------------------------------------------------------------------
-// Wave-level list staging.
+// Wave-level list staging (called by one wavefront: the group's first).
 
 __device__ __forceinline__ void stage_push(uint32_t *st, uint32_t &n, uint32_t v, uint32_t *counter, uint32_t *list)
 {
@@ -165,14 +271,61 @@ __device__ __forceinline__ void stage_push(uint32_t *st, uint32_t &n, uint32_t v
     }
 }
 
-// Compact the candidate flags cf[0..V) into `out` (ascending interior index),
-// clearing them; returns the count (wave-uniform).
-template <int E, typename FT> __device__ __forceinline__ int compact(WaveLds<E, FT> &L, uint16_t *out)
+// Set candidate flag q if `on`.  Byte flags take a store under the lane
+// mask (lanes writing a shared spare byte instead all hit one LDS bank);
+// bit flags an LDS atomic OR.
+template <int E, typename FT, int G>
+__device__ __forceinline__ void mark_cand(TileLds<E, FT, G> &L, bool on, int q)
+{
+    if constexpr (TileLds<E, FT, G>::BITS) {
+        if (on) atomicOr(&L.cfw[q >> 5], 1u << (q & 31));
+    } else {
+        if (on) L.cf[q] = 1;
+    }
+}
+
+// Compact the candidate flags into the list (ascending interior index within
+// each wavefront's part), clearing them; returns the count (group-uniform).
+// One wavefront: byte flags, one list.  A workgroup: bit flags; wavefront w
+// owns interior cells [w 64 C, (w + 1) 64 C) (C = V / G cells per thread) and
+// writes its candidates to the same range of the list, its count to gcnt[w].
+template <int E, typename FT, int G> __device__ __forceinline__ int compact(TileLds<E, FT, G> &L)
 {
     constexpr int K = Geo<E>::K;
     const int lane = threadIdx.x & 63;
+    uint16_t *out = L.list;
     uint32_t cnt = 0;
-    if constexpr (K % 8 == 0) {
+    if constexpr (G > 64) {
+        constexpr int C = Geo<E>::V / G;
+        static_assert(C >= 1 && C <= 32 && 32 % C == 0, "cells per thread must divide a word");
+        const int r = Grp<G>::rank(), wv = Grp<G>::wave();
+        const int word = (r * C) >> 5, sh = (r * C) & 31;
+        const uint32_t wbits = L.cfw[word];
+        uint32_t bits = C == 32 ? wbits : (wbits >> sh) & ((1u << (C & 31)) - 1u);
+        cnt = (uint32_t)__popc(bits);
+        uint32_t pre = 0, total = 0;
+        const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int b = 0; (1 << b) <= C; b++) {
+            const unsigned long long m = __ballot((cnt >> b) & 1u);
+            pre += (uint32_t)__popcll(m & lt) << b;
+            total += (uint32_t)__popcll(m) << b;
+        }
+        uint16_t *seg = out + wv * 64 * C;
+        while (bits) {
+            const int b = __builtin_ctz(bits);
+            seg[pre++] = (uint16_t)(r * C + b);
+            bits &= bits - 1u;
+        }
+        // every lane sharing the word read it above (same wavefront)
+        if (sh == 0 && wbits) L.cfw[word] = 0u;
+        if (lane == 0) L.gcnt[wv] = total;
+        __syncthreads();
+        int n = 0;
+#pragma unroll
+        for (int k = 0; k < G / 64; k++) n += (int)L.gcnt[k];
+        return n;
+    } else if constexpr (K % 8 == 0) {
         // flags are 0/1 bytes: a 64-bit word holds 8 of them
         unsigned long long *w = (unsigned long long *)&L.cf[lane * K];
         unsigned long long x[K / 8];
@@ -233,18 +386,37 @@ template <int E, typename FT> __device__ __forceinline__ int compact(WaveLds<E, 
     }
 }
 
+// The k-th candidate of the last compaction.
+template <int E, typename FT, int G> __device__ __forceinline__ int cand_at(const TileLds<E, FT, G> &L, int k)
+{
+    if constexpr (G == 64) {
+        return L.list[k];
+    } else {
+        constexpr int C = Geo<E>::V / G;
+        int w = 0;
+#pragma unroll
+        for (int q = 0; q < G / 64 - 1; q++) {
+            if (k < (int)L.gcnt[w]) break;
+            k -= (int)L.gcnt[w];
+            w++;
+        }
+        return L.list[w * 64 * C + k];
+    }
+}
+
 // Mark the updatable interior neighbours of interior point p (domain cell d)
 // that lie downwind of the value magnitude a: only they can use p as an
 // upwind point (the |T_lmn| > |T_ijk| guard of Alg. 10).
-template <int E, typename FT> __device__ __forceinline__ void mark_nbrs(WaveLds<E, FT> &L, int p, int d, double a)
+template <int E, typename FT, int G>
+__device__ __forceinline__ void mark_nbrs(TileLds<E, FT, G> &L, int p, int d, double a)
 {
-    using G = Geo<E>;
-    if ((L.fl[d - G::OX] & FL_UPD) && fabs(L.T[d - G::OX]) > a) L.cf[p - E * E] = 1;
-    if ((L.fl[d + G::OX] & FL_UPD) && fabs(L.T[d + G::OX]) > a) L.cf[p + E * E] = 1;
-    if ((L.fl[d - G::OY] & FL_UPD) && fabs(L.T[d - G::OY]) > a) L.cf[p - E] = 1;
-    if ((L.fl[d + G::OY] & FL_UPD) && fabs(L.T[d + G::OY]) > a) L.cf[p + E] = 1;
-    if ((L.fl[d - G::OZ] & FL_UPD) && fabs(L.T[d - G::OZ]) > a) L.cf[p - 1] = 1;
-    if ((L.fl[d + G::OZ] & FL_UPD) && fabs(L.T[d + G::OZ]) > a) L.cf[p + 1] = 1;
+    using Gm = Geo<E>;
+    if ((L.fl[d - Gm::OX] & FL_UPD) && fabs(L.T[d - Gm::OX]) > a) mark_cand(L, true, p - E * E);
+    if ((L.fl[d + Gm::OX] & FL_UPD) && fabs(L.T[d + Gm::OX]) > a) mark_cand(L, true, p + E * E);
+    if ((L.fl[d - Gm::OY] & FL_UPD) && fabs(L.T[d - Gm::OY]) > a) mark_cand(L, true, p - E);
+    if ((L.fl[d + Gm::OY] & FL_UPD) && fabs(L.T[d + Gm::OY]) > a) mark_cand(L, true, p + E);
+    if ((L.fl[d - Gm::OZ] & FL_UPD) && fabs(L.T[d - Gm::OZ]) > a) mark_cand(L, true, p - 1);
+    if ((L.fl[d + Gm::OZ] & FL_UPD) && fabs(L.T[d + Gm::OZ]) > a) mark_cand(L, true, p + 1);
 }
 
 // A domain cell is a source of the relaxation when it is a seed, or when its
@@ -259,8 +431,8 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 }
 
 // r = h / F of interior point p (+inf for seeds and impassable cells).
-template <int E, typename FT>
-__device__ __forceinline__ double cell_r(const WaveLds<E, FT> &L, int p, double h)
+template <int E, typename FT, int G>
+__device__ __forceinline__ double cell_r(const TileLds<E, FT, G> &L, int p, double h)
 {
     if constexpr (sizeof(FT) == 8)
         return L.F[p];
@@ -282,19 +454,19 @@ __device__ __forceinline__ double cell_r(const WaveLds<E, FT> &L, int p, double 
 // still an upper bound of the final value at p; when that neighbour later
 // becomes a source with a smaller value it marks p again, so the fixed point
 // (the discrete system of Eq. 2-3) is the same.
-template <int E, typename FT, bool AN, bool TWO>
-__device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacing &sp, int p, double h,
+template <int E, typename FT, int G, bool AN, bool TWO>
+__device__ __forceinline__ bool eval_point(const TileLds<E, FT, G> &L, const Spacing &sp, int p, double h,
                                            const double bnd[2], double &out,
                                            double &vp, double na[6])
 {
-    using G = Geo<E>;
-    const int d = G::domp(p);
+    using Gm = Geo<E>;
+    const int d = Gm::domp(p);
     vp = L.T[d];
     if constexpr (!TWO) {
         double m[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
-            const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
+            const int off = ax == 0 ? Gm::OX : ax == 1 ? Gm::OY : Gm::OZ;
             na[2 * ax] = L.T[d - off];
             na[2 * ax + 1] = L.T[d + off];
             m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
@@ -311,7 +483,7 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
     double am[3], ap3[3];  // per-axis minima for side - and side +
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
-        const int off = ax == 0 ? G::OX : ax == 1 ? G::OY : G::OZ;
+        const int off = ax == 0 ? Gm::OX : ax == 1 ? Gm::OY : Gm::OZ;
         double mneg = FMM_INF, mpos = FMM_INF;
 #pragma unroll
         for (int s = 0; s < 2; s++) {
@@ -356,37 +528,41 @@ __device__ __forceinline__ bool eval_point(const WaveLds<E, FT> &L, const Spacin
 }
 
 // Relaxation at level th until no candidate improves; returns the number of
-// rounds.  Candidates are taken 64 at a time: all evaluations of a chunk read
-// before any of its writes, later chunks see earlier ones (the fixed point is
-// the same either way).
+// rounds.  Candidates are taken G at a time.  In a one-wavefront group all
+// evaluations of a chunk read before any of its writes and later chunks see
+// earlier ones.  In a workgroup the threads write as they finish: a read
+// racing with a write returns the old or the new value, both upper bounds of
+// the neighbour's final value, and a write that can lower a neighbour marks
+// it for the next round, so the fixed point is the same either way.
 // Neighbours are marked from the magnitudes the evaluation read; values only
 // decrease, so a neighbour lowered meanwhile is at worst marked needlessly,
 // never missed.
-template <int E, typename FT, bool AN, bool TWO>
-__device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double h, const double th[2], WaveState &ws)
+template <int E, typename FT, int G, bool AN, bool TWO>
+__device__ __forceinline__ int relax(const Params &P, TileLds<E, FT, G> &L, double h, const double th[2],
+                                     WaveState &ws)
 {
-    using G = Geo<E>;
-    const int lane = threadIdx.x & 63;
-    int n = compact(L, L.list);
+    using Gm = Geo<E>;
+    const int r = Grp<G>::rank();
+    int n = compact(L);
     int rounds = 0;
     while (n > 0) {
         if (++rounds > MAX_ROUNDS) {
-            if (lane == 0) atomicOr(&P.ctrl->error_run, ERR_ROUNDS);
+            if (r == 0) atomicOr(&P.ctrl->error_run, ERR_ROUNDS);
             break;
         }
-        for (int base = 0; base < n; base += 64) {
-            const int k = base + lane;
+        for (int base = 0; base < n; base += G) {
+            const int k = base + r;
             double nv = 0.0, vp = 0.0, na[6];
             bool ch = false;
             int p = 0;
             if (k < n) {
-                p = L.list[k];
-                ch = eval_point<E, FT, AN, TWO>(L, P.sp, p, h, th, nv, vp, na);
+                p = cand_at(L, k);
+                ch = eval_point<E, FT, G, AN, TWO>(L, P.sp, p, h, th, nv, vp, na);
                 ws.n_solve++;
             }
-            wave_sync();
+            if constexpr (G == 64) wave_sync();
             if (ch) {
-                const int d = G::domp(p);
+                const int d = Gm::domp(p);
                 const uint8_t fo = L.fl[d];
                 // reopened: the old value was already a source.  The level
                 // never drops below the bound of the tile's previous march, so
@@ -398,39 +574,38 @@ __device__ __forceinline__ int relax(const Params &P, WaveLds<E, FT> &L, double 
                 L.fl[d] = fo | (src ? (uint8_t)(FL_CHG | FL_SRC) : (uint8_t)FL_CHG);
                 const double a = TWO ? fabs(nv) : nv;
                 if (src) {
-                    // mark the downwind interior neighbours; the others write
-                    // the spare flag cf[V] (no branches).  Seeds and
+                    // mark the downwind interior neighbours.  Seeds and
                     // impassable cells may be marked too: their LDS speed is
                     // 0, so their solve gives +inf and changes nothing.
-                    constexpr int V = G::V;
-                    const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
-                    L.cf[(i0 > 0 && na[0] > a) ? p - E * E : V] = 1;
-                    L.cf[(i0 < E - 1 && na[1] > a) ? p + E * E : V] = 1;
-                    L.cf[(i1 > 0 && na[2] > a) ? p - E : V] = 1;
-                    L.cf[(i1 < E - 1 && na[3] > a) ? p + E : V] = 1;
-                    L.cf[(i2 > 0 && na[4] > a) ? p - 1 : V] = 1;
-                    L.cf[(i2 < E - 1 && na[5] > a) ? p + 1 : V] = 1;
+                    const int i0 = p >> (2 * Gm::LOG), i1 = (p >> Gm::LOG) & (E - 1), i2 = p & (E - 1);
+                    mark_cand(L, i0 > 0 && na[0] > a, p - E * E);
+                    mark_cand(L, i0 < E - 1 && na[1] > a, p + E * E);
+                    mark_cand(L, i1 > 0 && na[2] > a, p - E);
+                    mark_cand(L, i1 < E - 1 && na[3] > a, p + E);
+                    mark_cand(L, i2 > 0 && na[4] > a, p - 1);
+                    mark_cand(L, i2 < E - 1 && na[5] > a, p + 1);
                 }
             }
-            wave_sync();
+            if constexpr (G == 64) wave_sync();
         }
-        n = compact(L, L.list);
+        if constexpr (G > 64) __syncthreads();
+        n = compact(L);
     }
     return rounds;
 }
 
 // Smallest pending band value per side above level th: interior band values,
 // and halo values next to an interior cell that is not yet a source (they
-// become sources of this tile later).  Wave-uniform result.
-template <int E, typename FT>
-__device__ __forceinline__ void band_min(const WaveLds<E, FT> &L, const double th[2], double &m0, double &m1)
+// become sources of this tile later).  Group-uniform result.
+template <int E, typename FT, int G>
+__device__ __forceinline__ void band_min(TileLds<E, FT, G> &L, const double th[2], double &m0, double &m1)
 {
-    using G = Geo<E>;
-    constexpr int V = G::V, FACE = G::FACE;
-    const int lane = threadIdx.x & 63;
+    using Gm = Geo<E>;
+    constexpr int V = Gm::V, FACE = Gm::FACE;
+    const int r = Grp<G>::rank();
     double a0 = FMM_INF, a1 = FMM_INF;
-    for (int p = lane; p < V; p += 64) {
-        const int d = G::domp(p);
+    for (int p = r; p < V; p += G) {
+        const int d = Gm::domp(p);
         if (!(L.fl[d] & FL_UPD)) continue;
         const double v = L.T[d];
         const double a = fabs(v);
@@ -442,37 +617,38 @@ __device__ __forceinline__ void band_min(const WaveLds<E, FT> &L, const double t
             }
         }
     }
-    for (int q = lane; q < 6 * FACE; q += 64) {
+    for (int q = r; q < 6 * FACE; q += G) {
         const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
         int c0, c1, c2;
         face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = G::dom(c0, c1, c2);
+        const int d = Gm::dom(c0, c1, c2);
         const double v = L.T[d];
         const double a = fabs(v);
         if (!(a < FMM_INF) || (L.fl[d] & FL_SEED)) continue;
         if (a <= (v < 0.0 ? th[0] : th[1])) continue;
         face_inner<E>(f, c0, c1, c2);
-        const int di = G::dom(c0, c1, c2);
+        const int di = Gm::dom(c0, c1, c2);
         if (!(L.fl[di] & FL_UPD) || (L.fl[di] & FL_SRC)) continue;
         if (v < 0.0)
             a0 = fmin(a0, a);
         else
             a1 = fmin(a1, a);
     }
-    m0 = wave_min(a0);
-    m1 = wave_min(a1);
+    grp_min2(L, a0, a1);
+    m0 = a0;
+    m1 = a1;
 }
 
 // Mark the candidates next to cells whose value lies in (lo, hi] of their
 // side: they become sources when the level rises from lo to hi.
-template <int E, typename FT>
-__device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double lo[2], const double hi[2])
+template <int E, typename FT, int G>
+__device__ __forceinline__ void mark_new_sources(TileLds<E, FT, G> &L, const double lo[2], const double hi[2])
 {
-    using G = Geo<E>;
-    constexpr int V = G::V, FACE = G::FACE;
-    const int lane = threadIdx.x & 63;
-    for (int p = lane; p < V; p += 64) {
-        const int d = G::domp(p);
+    using Gm = Geo<E>;
+    constexpr int V = Gm::V, FACE = Gm::FACE;
+    const int r = Grp<G>::rank();
+    for (int p = r; p < V; p += G) {
+        const int d = Gm::domp(p);
         if (!(L.fl[d] & FL_UPD)) continue;
         const double v = L.T[d];
         const double a = fabs(v);
@@ -482,21 +658,21 @@ __device__ __forceinline__ void mark_new_sources(WaveLds<E, FT> &L, const double
             mark_nbrs(L, p, d, a);
         }
     }
-    for (int q = lane; q < 6 * FACE; q += 64) {
+    for (int q = r; q < 6 * FACE; q += G) {
         const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
         int c0, c1, c2;
         face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = G::dom(c0, c1, c2);
+        const int d = Gm::dom(c0, c1, c2);
         const double v = L.T[d];
         const double a = fabs(v);
         const int s = v < 0.0 ? 0 : 1;
         if (!(a < FMM_INF && a > lo[s] && a <= hi[s]) || (L.fl[d] & FL_SEED)) continue;
         L.fl[d] |= FL_SRC;
         face_inner<E>(f, c0, c1, c2);
-        const int di = G::dom(c0, c1, c2);
-        if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > a) L.cf[(c0 * E + c1) * E + c2] = 1;
+        const int di = Gm::dom(c0, c1, c2);
+        if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > a) mark_cand(L, true, (c0 * E + c1) * E + c2);
     }
-    wave_sync();
+    Grp<G>::sync();
 }
 
 // What a tile march needs to know about the problem the tile belongs to.
@@ -507,7 +683,7 @@ struct TileGeo {
 };
 
 // ---------------------------------------------------------------------------
-// One activation of a tile by one wavefront: load tile + halo into LDS, relax
+// One activation of a tile by its group: load tile + halo into LDS, relax
 // its band up to the restart bound (Alg. 12 via Alg. 10/11), write back the
 // changed points, pass changed boundary values on to the neighbours (Alg.
 // 13-15), and record the tile's pending band minimum (the heap top of Alg. 16).
@@ -516,16 +692,19 @@ struct TileGeo {
 // earlier phase (visit stamp); otherwise its cells count as +inf, which is a
 // valid upper bound, and the writer's flag makes this tile read them again.
 
-template <int E, typename FT, bool AN>
-__device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, const TileGeo &G0, uint32_t t, int mode,
+template <int E, typename FT, int G, bool AN>
+__device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L, const TileGeo &G0, uint32_t t,
+                                           int mode,
                                            uint32_t dbits,
                                            const double bnd[2], const double lastb[2], uint32_t epoch, uint32_t phase,
                                            bool second, WaveState &ws, uint32_t *listNext, uint32_t *cntNext,
                                            uint32_t *dlist, uint32_t *cntD, uint32_t *dprod)
 {
-    using G = Geo<E>;
-    constexpr int V = G::V, FACE = G::FACE;
+    using Gm = Geo<E>;
+    constexpr int V = Gm::V, FACE = Gm::FACE;
     const int lane = threadIdx.x & 63;
+    const int rk = Grp<G>::rank();
+    const bool lead = Grp<G>::wave() == 0;  // the group's first wavefront
     const FT *__restrict__ Ft = (const FT *)P.Ft;
     double *__restrict__ Tt = P.Tt;
 
@@ -547,7 +726,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     // contiguous E^2 runs of the neighbour tile, axis-1 faces E runs of E,
     // axis-2 faces come from the neighbour's face buffer; +inf outside the
     // grid or for a tile not yet written in an earlier phase.
-    constexpr int NI = (V + 63) / 64, NF = (6 * FACE + 63) / 64;
+    constexpr int NI = (V + G - 1) / G, NF = (6 * FACE + G - 1) / G;
     constexpr int CI = NI < 8 ? NI : 8, CF = NF < 8 ? NF : 8;
     // the level the march starts at (the sources it loads)
     const double th0[2] = {mode == MODE_INIT ? -1.0 : lastb[0], mode == MODE_INIT ? -1.0 : lastb[1]};
@@ -557,7 +736,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         FT fi[CI];
 #pragma unroll
         for (int j = 0; j < CI; j++) {
-            const int p = lane + 64 * (j0 + j);
+            const int p = rk + G * (j0 + j);
             if (p < V) {
                 vi[j] = Tt[tbase + p];
                 fi[j] = Ft[tbase + p];
@@ -565,9 +744,9 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         }
 #pragma unroll
         for (int j = 0; j < CI; j++) {
-            const int p = lane + 64 * (j0 + j);
+            const int p = rk + G * (j0 + j);
             if (p < V) {
-                const int d = G::domp(p);
+                const int d = Gm::domp(p);
                 const bool seed = hasSeed && ((mask[p >> 6] >> (p & 63)) & 1ull);
                 const double tv = fresh ? FMM_INF : vi[j];
                 uint8_t f8 = seed ? FL_SEED : ((double)fi[j] > 0.0 ? FL_UPD : 0);
@@ -584,7 +763,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                 else
                     L.F[p] = fixed ? (FT)0 : fi[j];
                 L.fl[d] = f8;
-                L.cf[p] = 0;
+                if constexpr (!TileLds<E, FT, G>::BITS) L.cf[p] = 0;
             }
         }
     }
@@ -593,7 +772,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         uint32_t vis_h[CF], tf_h[CF];
 #pragma unroll
         for (int j = 0; j < CF; j++) {
-            const int q = lane + 64 * (j0 + j);
+            const int q = rk + G * (j0 + j);
             vis_h[j] = 0;
             tf_h[j] = 0;
             if (q < 6 * FACE) {
@@ -619,7 +798,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         }
 #pragma unroll
         for (int j = 0; j < CF; j++) {
-            const int q = lane + 64 * (j0 + j);
+            const int q = rk + G * (j0 + j);
             if (q < 6 * FACE) {
                 const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
                 const int ax = f >> 1;
@@ -639,7 +818,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
                     const int pn = (n0c * E + n1c) * E + n2c;
                     if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
                 }
-                const int d = G::dom(c0, c1, c2);
+                const int d = Gm::dom(c0, c1, c2);
                 if (is_source(v, fl, th0)) fl |= FL_SRC;
                 anyneg |= v < 0.0;
                 L.T[d] = v;
@@ -647,9 +826,11 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
             }
         }
     }
-    if (lane < 12) L.bm[lane] = bits_of(FMM_INF);
-    const bool two = __ballot(anyneg) != 0ull;  // both sides present: the general relaxation
-    wave_sync();
+    if constexpr (TileLds<E, FT, G>::BITS)
+        for (int q = rk; q < V / 32; q += G) L.cfw[q] = 0u;
+    if (rk < 12) L.bm[rk] = bits_of(FMM_INF);
+    const bool two = grp_any(L, anyneg);  // both sides present: the general relaxation
+    Grp<G>::sync();
 
     // ---- ordered relaxation.  Sources at level th are the seeds and the
     // cells with |T| <= th of their side (the KNOWN-class points of Alg. 11).
@@ -663,19 +844,19 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     double th[2] = {init ? -1.0 : lastb[0], init ? -1.0 : lastb[1]};
     if (init) {
         // Alg. 9: the neighbours of every seed (in the tile or its halo).
-        for (int p = lane; p < V; p += 64) {
-            const int d = G::domp(p);
+        for (int p = rk; p < V; p += G) {
+            const int d = Gm::domp(p);
             if (L.fl[d] & FL_SEED) mark_nbrs(L, p, d, fabs(L.T[d]));
         }
-        for (int q = lane; q < 6 * FACE; q += 64) {
+        for (int q = rk; q < 6 * FACE; q += G) {
             const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
             int c0, c1, c2;
             face_cell<E>(f, u, w, c0, c1, c2);
-            const int d = G::dom(c0, c1, c2);
+            const int d = Gm::dom(c0, c1, c2);
             face_inner<E>(f, c0, c1, c2);
-            const int di = G::dom(c0, c1, c2);
+            const int di = Gm::dom(c0, c1, c2);
             if ((L.fl[d] & FL_SEED) && (L.fl[di] & FL_UPD) && fabs(L.T[di]) > fabs(L.T[d]))
-                L.cf[(c0 * E + c1) * E + c2] = 1;
+                mark_cand(L, true, (c0 * E + c1) * E + c2);
         }
     } else if (dbits) {
         // interior cells next to a halo source on a face whose values changed
@@ -684,27 +865,27 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         // marks their neighbours when it reaches them (mark_new_sources), and
         // a band value never marks anything, so a cell gets a tentative value
         // only from an accepted neighbour, as in the sequential march.
-        for (int q = lane; q < 6 * FACE; q += 64) {
+        for (int q = rk; q < 6 * FACE; q += G) {
             const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
             if (!((dbits >> f) & 1u)) continue;
             int c0, c1, c2;
             face_cell<E>(f, u, w, c0, c1, c2);
-            const int dh = G::dom(c0, c1, c2);
+            const int dh = Gm::dom(c0, c1, c2);
             if (!(L.fl[dh] & FL_SRC)) continue;
             const double vh = fabs(L.T[dh]);
             face_inner<E>(f, c0, c1, c2);
-            const int di = G::dom(c0, c1, c2);
-            if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > vh) L.cf[(c0 * E + c1) * E + c2] = 1;
+            const int di = Gm::dom(c0, c1, c2);
+            if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > vh) mark_cand(L, true, (c0 * E + c1) * E + c2);
         }
     }
-    wave_sync();
+    Grp<G>::sync();
     int rounds = 0;
     double tm0, tm1;
     PROF_CLOCK(t_marked);
     PROF_ADD(3, t_marked - t_loaded);
     for (;;) {
         PROF_CLOCK(t_r0);
-        rounds += two ? relax<E, FT, AN, true>(P, L, G0.h, th, ws) : relax<E, FT, AN, false>(P, L, G0.h, th, ws);
+        rounds += two ? relax<E, FT, G, AN, true>(P, L, G0.h, th, ws) : relax<E, FT, G, AN, false>(P, L, G0.h, th, ws);
         PROF_CLOCK(t_r1);
         PROF_ADD(4, t_r1 - t_r0);
         PROF_ADD(8, 1);
@@ -721,8 +902,10 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         PROF_ADD(5, t_r2 - t_r1);
     }
     PROF_CLOCK(t_levels);
-    ws.n_round += (unsigned long long)rounds;
-    ws.n_march++;
+    if (lead) {
+        ws.n_round += (unsigned long long)rounds;
+        ws.n_march++;
+    }
     PROF_ADD(10 + mode, 1);
 
     // ---- write back (every cell on the first write of the tile, else the
@@ -733,14 +916,14 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
 #ifdef FMM_PROFILE
     bool any_chg = false;
 #endif
-    for (int p = lane; p < V; p += 64) {
-        const int d = G::domp(p);
+    for (int p = rk; p < V; p += G) {
+        const int d = Gm::domp(p);
         const bool chg = (L.fl[d] & FL_CHG) != 0;
 #ifdef FMM_PROFILE
         any_chg |= chg;
 #endif
         if (!(chg || fresh)) continue;
-        const int i0 = p >> (2 * G::LOG), i1 = (p >> G::LOG) & (E - 1), i2 = p & (E - 1);
+        const int i0 = p >> (2 * Gm::LOG), i1 = (p >> Gm::LOG) & (E - 1), i2 = p & (E - 1);
         const double v = L.T[d];
         Tt[tbase + p] = v;
         if (i2 == 0) P.Zf[((size_t)t * 2 + 0) * FACE + i0 * E + i1] = v;
@@ -751,12 +934,12 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         // of its current value (values only decrease), and a root from v
         // exceeds |v|; so |v| >= the halo magnitude means nothing to send
         const double av = fabs(v);
-        const uint32_t fm = (i0 == 0 && av < fabs(L.T[d - G::OX]) ? 1u : 0u) |
-                            (i0 == E - 1 && av < fabs(L.T[d + G::OX]) ? 2u : 0u) |
-                            (i1 == 0 && av < fabs(L.T[d - G::OY]) ? 4u : 0u) |
-                            (i1 == E - 1 && av < fabs(L.T[d + G::OY]) ? 8u : 0u) |
-                            (i2 == 0 && av < fabs(L.T[d - G::OZ]) ? 16u : 0u) |
-                            (i2 == E - 1 && av < fabs(L.T[d + G::OZ]) ? 32u : 0u);
+        const uint32_t fm = (i0 == 0 && av < fabs(L.T[d - Gm::OX]) ? 1u : 0u) |
+                            (i0 == E - 1 && av < fabs(L.T[d + Gm::OX]) ? 2u : 0u) |
+                            (i1 == 0 && av < fabs(L.T[d - Gm::OY]) ? 4u : 0u) |
+                            (i1 == E - 1 && av < fabs(L.T[d + Gm::OY]) ? 8u : 0u) |
+                            (i2 == 0 && av < fabs(L.T[d - Gm::OZ]) ? 16u : 0u) |
+                            (i2 == E - 1 && av < fabs(L.T[d + Gm::OZ]) ? 32u : 0u);
         if (!fm) continue;
         fany |= fm;
         if (is_source(v, 0, bnd)) {
@@ -772,15 +955,22 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     PROF_ADD(15, (__ballot(any_chg) == 0ull && mode == MODE_M2) ? 1 : 0);
 #endif
     uint32_t srcFaces = 0, anyFaces = 0;
+    if constexpr (G == 64) {
 #pragma unroll
-    for (int f = 0; f < 6; f++) {
-        if (__ballot((fsrc >> f) & 1u)) srcFaces |= 1u << f;
-        if (__ballot((fany >> f) & 1u)) anyFaces |= 1u << f;
+        for (int f = 0; f < 6; f++) {
+            if (__ballot((fsrc >> f) & 1u)) srcFaces |= 1u << f;
+            if (__ballot((fany >> f) & 1u)) anyFaces |= 1u << f;
+        }
+        wave_sync();
+    } else {
+        // also orders every write of the band minima bm before they are read
+        const uint32_t m = grp_or(L, fsrc | (fany << 8));
+        srcFaces = m & 0x3Fu;
+        anyFaces = (m >> 8) & 0x3Fu;
     }
-    wave_sync();
-    if (fresh && lane == 0) __hip_atomic_store(&P.visit[t], phase + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (fresh && rk == 0) __hip_atomic_store(&P.visit[t], phase + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    if (lane == 0) {
+    if (rk == 0) {
         TileMeta m;
         m.tmin[0] = tm0;
         m.tmin[1] = tm1;
@@ -792,9 +982,9 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
     ws.gmin1 = fmin(ws.gmin1, tm1);
 
     // ---- pass changed boundary values to the neighbours (Alg. 13-15).  Lane
-    // f < 6 handles face f and lane 6 the tile itself, so the atomics of all
-    // faces are in flight together.
-    {
+    // f < 6 of the group's first wavefront handles face f and lane 6 the tile
+    // itself, so the atomics of all faces are in flight together.
+    if (lead) {
         uint32_t u = 0;
         bool have = false, src = false;
         if (lane < 6 && ((anyFaces >> lane) & 1u)) {
@@ -848,7 +1038,7 @@ __device__ __forceinline__ void tile_march(const Params &P, WaveLds<E, FT> &L, c
         PROF_ADD(13, __popcll(__ballot(have && src)));
         PROF_ADD(14, __popcll(__ballot(have && !src)));
     }
-    wave_sync();
+    Grp<G>::sync();
     PROF_CLOCK(t_end);
     PROF_ADD(6, t_end - t_levels);
 }
@@ -911,11 +1101,13 @@ __device__ __forceinline__ void flush_acc(const Params &P, WaveState &ws, uint32
     ws.gmin0 = ws.gmin1 = FMM_INF;
 }
 
-template <int E, int NW, typename FT, bool AN>
-__device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, WgShared<NW> &S, int mode, uint32_t r,
+template <int E, int NW, typename FT, bool AN, int G>
+__device__ __forceinline__ void run_phase(const Params &P, TileLds<E, FT, G> &L, WgShared<NW> &S, int mode, uint32_t r,
                                           uint32_t phase, const uint32_t *items, uint32_t nitems, WaveState &ws)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int rk = Grp<G>::rank();
+    const bool lead = Grp<G>::wave() == 0;
     Ctrl *c = P.ctrl;
     Slot &cur = c->slot[r % 3];
     Slot &nxt = c->slot[(r + 1) % 3];
@@ -935,30 +1127,36 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
 
     // Dynamic distribution: the item list is cut into WORK_SEGS segments, one
     // per XCD (workgroups are dispatched to XCDs round robin), each with its
-    // own counter.  A wavefront claims items of its own segment one at a time
+    // own counter.  A group claims items of its own segment one at a time
     // and then helps with the others; the claim for the next item is issued
     // before the current one is marched so its latency overlaps the loads.
+    // In a workgroup group everything that steers the loop (claims, the abort
+    // flag, a tile's due test) is read by rank 0 and broadcast.
     uint32_t(*cnt)[32] = c->work[phase % 3];
     uint32_t seg = blockIdx.x % WORK_SEGS, left = WORK_SEGS;
     uint32_t claim = 0;
     InstView iv;
     iv.j = NO_INST;
-    if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
+    if (rk == 0) claim = atomicAdd(&cnt[seg][0], 1u);
     for (;;) {
-        const uint32_t k = bcast0(claim);
+        const uint32_t k = grp_bcast(L, claim);
         const uint32_t lo = (uint32_t)(((uint64_t)nitems * seg) / WORK_SEGS);
         const uint32_t hi = (uint32_t)(((uint64_t)nitems * (seg + 1)) / WORK_SEGS);
         if (k >= hi - lo) {
             if (--left == 0) break;
             seg = (seg + 1) % WORK_SEGS;
-            if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
+            if (rk == 0) claim = atomicAdd(&cnt[seg][0], 1u);
             continue;
         }
-        if (lane == 0) claim = atomicAdd(&cnt[seg][0], 1u);
+        if (rk == 0) claim = atomicAdd(&cnt[seg][0], 1u);
         // the item and the abort flag are requested together (one round trip)
         const uint32_t i = lo + k;
         const uint32_t item = items[i];
-        if (ld_acq(&c->abort)) break;
+        if constexpr (G == 64) {
+            if (ld_acq(&c->abort)) break;
+        } else {
+            if (grp_bcast(L, rk == 0 ? ld_acq(&c->abort) : 0u)) break;
+        }
         const uint32_t t = __builtin_amdgcn_readfirstlane(item);
         const uint32_t j = P.n_inst == 1 ? 0u : __builtin_amdgcn_readfirstlane(P.tinst[t]);
         if (j != iv.j) load_inst(P, j, r, mode, iv);
@@ -971,8 +1169,7 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
         uint32_t dbits = 0;
         double lastb[2] = {-FMM_INF, -FMM_INF};
         if (mode != MODE_INIT) {
-            if (lane == 0) dbits = atomicExch(&dcons[t], 0u);
-            dbits = bcast0(dbits);
+            if (rk == 0) dbits = atomicExch(&dcons[t], 0u);
             const TileMeta m = P.meta[t];
             lastb[0] = m.lastb[0];
             lastb[1] = m.lastb[1];
@@ -982,15 +1179,33 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             unsigned long long xb[6];
 #pragma unroll
             for (int q = 0; q < 6; q++) xb[q] = ld_acq64(&tx[q]);
-            const double p0 = fmin(m.tmin[0], fmin(bitsd(xb[0]), fmin(bitsd(xb[2]), bitsd(xb[4]))));
-            const double p1 = fmin(m.tmin[1], fmin(bitsd(xb[1]), fmin(bitsd(xb[3]), bitsd(xb[5]))));
+            double p0 = fmin(m.tmin[0], fmin(bitsd(xb[0]), fmin(bitsd(xb[2]), bitsd(xb[4]))));
+            double p1 = fmin(m.tmin[1], fmin(bitsd(xb[1]), fmin(bitsd(xb[3]), bitsd(xb[5]))));
+            if constexpr (G == 64) {
+                dbits = bcast0(dbits);
+            } else {
+                // neighbours may be writing the current phase's slots: rank 0's
+                // reading decides for the whole group
+                if (rk == 0) {
+                    L.bc[1] = dbits;
+                    L.bc[2] = (uint32_t)bits_of(p0);
+                    L.bc[3] = (uint32_t)(bits_of(p0) >> 32);
+                    L.bc[4] = (uint32_t)bits_of(p1);
+                    L.bc[5] = (uint32_t)(bits_of(p1) >> 32);
+                }
+                __syncthreads();
+                dbits = L.bc[1];
+                p0 = bitsd((unsigned long long)L.bc[2] | ((unsigned long long)L.bc[3] << 32));
+                p1 = bitsd((unsigned long long)L.bc[4] | ((unsigned long long)L.bc[5] << 32));
+                __syncthreads();
+            }
             const bool due =
                 dbits != 0 || (p0 < FMM_INF && p0 <= iv.bnd[0]) || (p1 < FMM_INF && p1 <= iv.bnd[1]);
             if (!due) {
                 // carried over unchanged to the next restart
                 ws.gmin0 = fmin(ws.gmin0, p0);
                 ws.gmin1 = fmin(ws.gmin1, p1);
-                if (p0 < FMM_INF || p1 < FMM_INF) {
+                if (lead && (p0 < FMM_INF || p1 < FMM_INF)) {
                     uint32_t oe = 0;
                     if (lane == 0) oe = atomicExch(&P.epoch[t], epoch);
                     oe = bcast0(oe);
@@ -1002,16 +1217,16 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
             // the march reads the whole halo, so the values passed on in earlier
             // phases (whose data the barrier made visible) are consumed; the
             // current phase's slot stays for a later march
-            if (lane == 0) {
+            if (rk == 0) {
 #pragma unroll
                 for (int q = 0; q < 6; q++)
                     if ((uint32_t)(q >> 1) != phase % 3u && xb[q] != bits_of(FMM_INF))
                         atomicExch(&tx[q], bits_of(FMM_INF));
             }
-            wave_sync();
+            Grp<G>::sync();
         }
-        tile_march<E, FT, AN>(P, L, iv.g, t, mode, dbits, iv.bnd, lastb, epoch, phase, second, ws, listNext,
-                          &nxt.live_len, P.dlist, &cur.d_len, dprod);
+        tile_march<E, FT, G, AN>(P, L, iv.g, t, mode, dbits, iv.bnd, lastb, epoch, phase, second, ws, listNext,
+                                 &nxt.live_len, P.dlist, &cur.d_len, dprod);
     }
 
     PROF_CLOCK(t_phase1);
@@ -1068,13 +1283,16 @@ __device__ __forceinline__ void run_phase(const Params &P, WaveLds<E, FT> &L, Wg
     ws.gmin0 = ws.gmin1 = FMM_INF;
 }
 
-template <int E, int NW, typename FT, bool AN>
-__global__ void __launch_bounds__(NW * 64) k_driver(Params P)
+// NW wavefronts per workgroup in groups of G threads; WPE is the occupancy
+// the register budget is fitted to (wavefronts per SIMD).
+template <int E, int NW, typename FT, bool AN, int G, int WPE>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE))) k_driver(Params P)
 {
-    __shared__ WaveLds<E, FT> s_wave[NW];
+    static_assert(G == 64 || G == NW * 64, "a group is one wavefront or the whole workgroup");
+    __shared__ TileLds<E, FT, G> s_tile[NW * 64 / G];
     __shared__ WgShared<NW> s_g;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    WaveLds<E, FT> &L = s_wave[wid];
+    TileLds<E, FT, G> &L = s_tile[G == 64 ? wid : 0];
     Ctrl *c = P.ctrl;
     const uint32_t nwg = gridDim.x;
     uint32_t gen = 0;
@@ -1104,7 +1322,7 @@ __global__ void __launch_bounds__(NW * 64) k_driver(Params P)
     bool run = ld_acq(&c->error) == 0;
     while (run) {
         PROF_CLOCK(t_p0);
-        run_phase<E, NW, FT, AN>(P, L, s_g, mode, r, phase, items, nitems, ws);
+        run_phase<E, NW, FT, AN, G>(P, L, s_g, mode, r, phase, items, nitems, ws);
         PROF_CLOCK(t_p1);
         const bool passed = grid_barrier(c, gen, nwg, &s_g.ok);
         PROF_CLOCK(t_p2);
@@ -1556,11 +1774,11 @@ hipError_t launch_prepare(const Params &P, const Inst *insts, int64_t n, int E, 
     }
 }
 
-template <int E, int NW, typename FT, bool AN>
+template <int E, int NW, typename FT, bool AN, int G, int WPE>
 static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_out)
 {
     static int occ = -1;
-    auto kern = k_driver<E, NW, FT, AN>;
+    auto kern = k_driver<E, NW, FT, AN, G, WPE>;
     if (occ < 0) {
         int nb = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NW * 64, 0);
@@ -1590,16 +1808,20 @@ static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_
 // so the uniform-grid march carries none of its code.
 template <bool AN> static hipError_t launch_driver_a(const Params &P, int E, bool f64, hipStream_t s, uint32_t *nwg_out)
 {
+    // 4^3 and 8^3 tiles: one wavefront per tile, one workgroup per CU (three
+    // wavefronts per SIMD).  16^3 tiles: one workgroup per tile, four
+    // wavefronts and two tiles per CU with FP32 speeds (the LDS of two fits),
+    // eight wavefronts and one tile per CU with FP64 speeds.
     switch (E) {
     case 4:
-        return f64 ? launch_driver_t<4, 12, double, AN>(P, s, nwg_out)
-                   : launch_driver_t<4, 12, float, AN>(P, s, nwg_out);
+        return f64 ? launch_driver_t<4, 12, double, AN, 64, 3>(P, s, nwg_out)
+                   : launch_driver_t<4, 12, float, AN, 64, 3>(P, s, nwg_out);
     case 8:
-        return f64 ? launch_driver_t<8, FMM_E8_WAVES_F64, double, AN>(P, s, nwg_out)
-                   : launch_driver_t<8, FMM_E8_WAVES_F32, float, AN>(P, s, nwg_out);
+        return f64 ? launch_driver_t<8, FMM_E8_WAVES_F64, double, AN, 64, 3>(P, s, nwg_out)
+                   : launch_driver_t<8, FMM_E8_WAVES_F32, float, AN, 64, 3>(P, s, nwg_out);
     case 16:
-        return f64 ? launch_driver_t<16, 1, double, AN>(P, s, nwg_out)
-                   : launch_driver_t<16, 1, float, AN>(P, s, nwg_out);
+        return f64 ? launch_driver_t<16, 8, double, AN, 512, 2>(P, s, nwg_out)
+                   : launch_driver_t<16, 4, float, AN, 256, 2>(P, s, nwg_out);
     default: return hipErrorInvalidValue;
     }
 }

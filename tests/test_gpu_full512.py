@@ -2,7 +2,8 @@
 512^3 (1.34e8 points): FP32 speeds clip(exp(0.5 g), 0.25, 4) with correlation
 length 0.05, four point sources, full march, 8^3 tiles.  Every point of the
 grid is compared with the oracle's sequential solve at the paper's stride
-(2h) and at the benchmark's (4h): identical status bytes and max |dT| <=
+(2h) and at the benchmark's (4h), with 8^3 tiles and with 16^3 blocks
+marched by whole workgroups: identical status bytes and max |dT| <=
 1e-12 max|T| (the paper's parallel-against-sequential accuracy check, Sec.
 5.2, on the timed configuration)."""
 import numpy as np
@@ -27,10 +28,12 @@ def test_full_parity_512(oracle_mod):
     w = inputs.random_speed(n=N1D, seed=0, device=dev)
     print(f"random_speed_{N1D}: F {inputs.fingerprint(w.F)}, sources {w.meta['sources']}", flush=True)
     res = {}
-    for sh in (2.0, 4.0):
-        T, st, stats = fmm.solve(w.F, w.h, w.seed_idx, w.seed_val, stride=sh * w.h, tile_edge=8, time_limit_s=100)
-        res[sh] = (T.cpu().numpy(), st.cpu().numpy(), stats)
-        print(f"gpu stride {sh}h: {stats.n_restarts} restarts, {stats.n_accepted} accepted", flush=True)
+    for edge, sh in ((8, 2.0), (8, 4.0), (16, 4.0)):
+        T, st, stats = fmm.solve(w.F, w.h, w.seed_idx, w.seed_val, stride=sh * w.h, tile_edge=edge,
+                                 time_limit_s=100)
+        res[(edge, sh)] = (T.cpu().numpy(), st.cpu().numpy(), stats)
+        print(f"gpu {edge}^3 tiles, stride {sh}h: {stats.n_restarts} restarts, {stats.n_accepted} accepted",
+              flush=True)
         del T, st
     F, idx, val = w.numpy()
     del w
@@ -38,9 +41,9 @@ def test_full_parity_512(oracle_mod):
     To, so, sto, _ = oracle_mod.solve(F, 1.0 / (N1D - 1), idx, val)
     print(f"oracle: {sto.n_accepted} accepted, max|T| {sto.max_abs_T}", flush=True)
     assert sto.n_accepted == N1D ** 3 - len(idx)
-    for sh, (Tg, sg, stats) in res.items():
+    for (edge, sh), (Tg, sg, stats) in res.items():
         rep = parity_report(Tg, sg, To, so)
-        print(f"stride {sh}h: {rep}", flush=True)
+        print(f"{edge}^3 tiles, stride {sh}h: {rep}", flush=True)
         assert rep["same_status"], rep
         assert rep["rel"] <= TOL, rep
         assert stats.n_accepted == sto.n_accepted

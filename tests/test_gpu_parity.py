@@ -105,10 +105,11 @@ def test_single_tile_infinite_stride_two_restarts(fmm, oracle_mod):
     assert_parity(Tg, sg, To, so)
 
 
+@pytest.mark.parametrize("edge", [8, 16])
 @pytest.mark.parametrize("stride_h", [2.0, math.inf, 0.5])
-def test_point_source_64(fmm, oracle_mod, stride_h):
+def test_point_source_64(fmm, oracle_mod, stride_h, edge):
     w = inputs.point_source(64)
-    Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h)
+    Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, tile_edge=edge)
     To, so, sto = oracle_solve(oracle_mod, w)
     assert st.n_accepted == sto.n_accepted == 64 ** 3 - 1
     assert_parity(Tg, sg, To, so)
@@ -128,14 +129,26 @@ def test_random_speed_parity(fmm, oracle_mod, edge, shape, seed, nsrc, dtype, ze
         assert_parity(Tg, sg, To, so)
 
 
+@pytest.mark.parametrize("edge", [8, 16])
+def test_many_tiles_parity(fmm, oracle_mod, edge):
+    """A grid of several hundred 16^3 (or thousands of 8^3) tiles with a
+    ragged tail on every axis, FP32 speeds and impassable cells."""
+    w = inputs.random_small((101, 87, 118), n_sources=5, seed=31, dtype=torch.float32, zero_frac=0.03)
+    To, so, _ = oracle_solve(oracle_mod, w)
+    for stride_h in (1.5, 4.0, 8.0):
+        Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, tile_edge=edge)
+        assert_parity(Tg, sg, To, so)
+
+
 @pytest.mark.parametrize("width", [0.1, math.inf])
 def test_two_sided_spheres(fmm, oracle_mod, width):
     w = inputs.spheres(n=48, n_spheres=5, seed=1, width=width)
     To, so, _ = oracle_solve(oracle_mod, w)
     assert np.any(so & 0x80)
-    for stride_h in (2.0, 4.0):
-        Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h)
-        assert_parity(Tg, sg, To, so, allow_edge=width if math.isfinite(width) else None)
+    for edge in (8, 16):
+        for stride_h in (2.0, 4.0):
+            Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, tile_edge=edge)
+            assert_parity(Tg, sg, To, so, allow_edge=width if math.isfinite(width) else None)
 
 
 def test_sphere_reinit_256(fmm, oracle_mod):
@@ -150,6 +163,9 @@ def test_sphere_reinit_256(fmm, oracle_mod):
         rep = assert_parity(Tg, sg, To, so, allow_edge=w.width)
         print(f"spheres_256 stride {stride_h}h", rep, st.as_dict(), flush=True)
         runs[stride_h] = (Tg, sg)
+    Tg, sg, st = gpu_solve(fmm, w, stride=4.0 * w.h, tile_edge=16)
+    rep = assert_parity(Tg, sg, To, so, allow_edge=w.width)
+    print("spheres_256 stride 4h, 16^3 tiles", rep, st.as_dict(), flush=True)
     T2, s2, _ = gpu_solve(fmm, w, stride=4.0 * w.h)
     T1, s1 = runs[4.0]
     both = ((s1 & 3) >= 2) & ((s2 & 3) >= 2)
@@ -248,18 +264,19 @@ def test_restart_limit(fmm):
     assert ei.value.code == fmm.FMM_ENOCONV
 
 
+@pytest.mark.parametrize("edge", [8, 16])
 @pytest.mark.parametrize("shape,seed", [((37, 29, 45), 1), ((33, 40, 18), 2)])
-def test_one_march_per_restart_parity(fmm, oracle_mod, shape, seed):
+def test_one_march_per_restart_parity(fmm, oracle_mod, shape, seed, edge):
     """FMM_ONE_MARCH defers the second march of Alg. 16 to the next restart;
     the solution must not change."""
     w = inputs.random_small(shape, n_sources=2, seed=seed, zero_frac=0.05)
     To, so, _ = oracle_solve(oracle_mod, w)
     for stride_h in (0.5, 2.0, 4.0, math.inf):
-        Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, one_march=True)
+        Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, one_march=True, tile_edge=edge)
         assert_parity(Tg, sg, To, so)
     w2 = inputs.spheres(n=40, n_spheres=4, seed=3, width=0.12)
     To, so, _ = oracle_solve(oracle_mod, w2)
-    Tg, sg, st = gpu_solve(fmm, w2, one_march=True)
+    Tg, sg, st = gpu_solve(fmm, w2, one_march=True, tile_edge=edge)
     assert_parity(Tg, sg, To, so, allow_edge=w2.width)
 
 
