@@ -1479,33 +1479,69 @@ __global__ void k_init_ws(Params P, int E)
     for (int64_t i = i0; i < nm; i += stride) P.mask[i] = 0ull;
 }
 
+// LDS-staged conversion between a row-major grid and the tiled layout.  A
+// work unit is an E x E bundle of grid rows (one tile row along axes 0 and 1)
+// over a chunk of CH consecutive tiles along axis 2.  Those CH tiles are
+// consecutive in the tiled layout, so the tiled side of a unit is one
+// contiguous run of CH * V values and the row-major side is E * E row pieces
+// of CH * E contiguous values: both sides stream in long runs.  Tiles are E
+// values apart in LDS beyond their V values, which puts the E row pieces of a
+// wavefront's 64 consecutive columns in distinct banks.
+constexpr int STAGE_THREADS = 256;
+constexpr int STAGE_BATCH = 8;  // loads a thread keeps in flight
+template <int E, typename T> struct Stage {
+    static constexpr int V = E * E * E;
+    static constexpr int CH = E == 16 ? (sizeof(T) == 8 ? 2 : 4) : E == 8 ? (sizeof(T) == 8 ? 8 : 16) : 32;
+    static constexpr int W = CH * E;  // columns of a row piece
+    static constexpr int R = E * E;   // row pieces of a unit
+    static constexpr int TS = V + E;  // LDS stride of one tile
+};
+
 // Tiled copy of one problem's speeds (0 outside its grid) and the problem
-// index of each of its tiles.  One workgroup per tile.
-template <int E, typename FT> __global__ void k_tile_speed(Params P, Inst I, uint32_t j)
+// index of each of its tiles.
+template <int E, typename FT> __global__ void __launch_bounds__(STAGE_THREADS) k_tile_speed(Params P, Inst I, uint32_t j)
 {
-    // A workgroup of E wavefronts takes one slab: a plane i0 (padded to whole
-    // tiles) and one row of tiles along axis 1; wavefront w reads grid row
-    // i1 = E ty + w.  Each row is read contiguously, and together the E
-    // wavefronts fill E x E contiguous values of every tile they cross.
-    // Cells outside the grid get speed 0 (impassable).
-    constexpr int V = E * E * E;
+    using S = Stage<E, FT>;
+    constexpr int V = S::V, CH = S::CH, W = S::W, R = S::R, TS = S::TS;
+    constexpr int NL = R * W / STAGE_THREADS, NS = CH * V / STAGE_THREADS;  // values per thread and side
+    __shared__ FT buf[CH * TS];
     const FT *F = (const FT *)I.F;
     FT *Ft = (FT *)P.Ft;
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t n12 = I.n1 * I.n2, slabs = (int64_t)I.t0 * E * I.t1, len2 = (int64_t)I.t2 * E;
-    for (int64_t sl = blockIdx.x; sl < slabs; sl += gridDim.x) {
-        const int64_t i0 = sl / I.t1, ty = sl - i0 * I.t1, i1 = ty * E + w;
-        const bool row_in = i0 < I.n0 && i1 < I.n1;
-        const size_t trow = (size_t)I.base + (size_t)(((i0 / E) * I.t1 + ty) * I.t2);
-        const int prow = (int)(((i0 % E) * E + w) * E);
-        for (int64_t i2 = lane; i2 < len2; i2 += 64) {
-            FT f = (FT)0;
-            if (row_in && i2 < I.n2) f = F[i0 * n12 + i1 * I.n2 + i2];
-            const size_t t = trow + (size_t)(i2 / E);
-            Ft[t * V + prow + (int)(i2 % E)] = f;
-            if (prow == 0 && i2 % E == 0) P.tinst[t] = j;
+    const int64_t nch = (I.t2 + CH - 1) / CH;
+    const int64_t units = (int64_t)I.t0 * I.t1 * nch;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t cc = u % nch, ab = u / nch, b = ab % I.t1, a = ab / I.t1;
+        const int64_t c0 = cc * CH;
+        const int nt = (int)(I.t2 - c0 < CH ? I.t2 - c0 : CH);
+        // eight loads of the thread are in flight before the first is used
+        for (int q0 = 0; q0 < NL; q0 += STAGE_BATCH) {
+            FT v[STAGE_BATCH];
+#pragma unroll
+            for (int q = 0; q < STAGE_BATCH; q++) {
+                const int idx = (int)threadIdx.x + (q0 + q) * STAGE_THREADS;
+                const int r = idx / W, c = idx - r * W;
+                const int64_t i0 = a * E + r / E, i1 = b * E + r % E, i2 = c0 * E + c;
+                v[q] = (FT)0;
+                if (q0 + q < NL && c / E < nt && i0 < I.n0 && i1 < I.n1 && i2 < I.n2)
+                    v[q] = F[(i0 * I.n1 + i1) * I.n2 + i2];
+            }
+#pragma unroll
+            for (int q = 0; q < STAGE_BATCH; q++) {
+                const int idx = (int)threadIdx.x + (q0 + q) * STAGE_THREADS;
+                const int r = idx / W, c = idx - r * W;
+                if (q0 + q < NL) buf[(c / E) * TS + r * E + c % E] = v[q];
+            }
         }
+        __syncthreads();
+        const size_t t0 = (size_t)I.base + (size_t)((a * I.t1 + b) * I.t2 + c0);
+#pragma unroll 8
+        for (int q = 0; q < NS; q++) {
+            const int idx = (int)threadIdx.x + q * STAGE_THREADS;
+            const int k = idx / V;
+            if (k < nt) Ft[t0 * V + idx] = buf[k * TS + (idx - k * V)];
+        }
+        if ((int)threadIdx.x < nt) P.tinst[t0 + threadIdx.x] = j;
+        __syncthreads();
     }
 }
 
@@ -1620,55 +1656,84 @@ template <typename FT> __global__ void k_validate(Params P, Inst I)
 
 // ---------------------------------------------------------------------------
 // Finalize one problem: row-major T (accepted points and seeds keep their
-// values, all others +inf), status bytes and statistics.  A workgroup of E
-// wavefronts takes a slab (a plane i0 and one row of tiles along axis 1);
-// wavefront w writes grid row i1 = E ty + w, so the E wavefronts together read
-// E x E contiguous values of every tile they cross.
+// values, all others +inf), status bytes and statistics.  Work units as for
+// the speeds: a unit reads its CH tiles as one contiguous run (tiles never
+// written are skipped: they hold +inf) and writes E * E row pieces.
 
-template <int E> __global__ void k_finalize(Params P, Inst I, uint32_t j)
+template <int E> __global__ void __launch_bounds__(STAGE_THREADS) k_finalize(Params P, Inst I, uint32_t j)
 {
-    constexpr int V = E * E * E;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t slabs = I.n0 * I.t1;
+    using S = Stage<E, double>;
+    constexpr int V = S::V, CH = S::CH, W = S::W, R = S::R, TS = S::TS;
+    constexpr int NL = CH * V / STAGE_THREADS, NS = R * W / STAGE_THREADS;  // values per thread and side
+    __shared__ double buf[CH * TS];
+    __shared__ uint32_t s_vis[CH], s_tf[CH];
+    const int64_t nch = (I.t2 + CH - 1) / CH;
+    const int64_t units = (int64_t)I.t0 * I.t1 * nch;
     unsigned long long acc = 0;
     double mx = 0.0;
-    for (int64_t sl = blockIdx.x; sl < slabs; sl += gridDim.x) {
-        const int64_t i0 = sl / I.t1, ty = sl - i0 * I.t1, i1 = ty * E + wv;
-        if (i1 >= I.n1) continue;
-        const int64_t row = i0 * I.n1 + i1;
-        const uint32_t trow = I.base + (uint32_t)(((i0 / E) * I.t1 + ty) * I.t2);
-        const int prow = (int)(((i0 % E) * E + wv) * E);
-        for (int64_t i2 = threadIdx.x & 63; i2 < I.n2; i2 += 64) {
-            const int64_t g = row * I.n2 + i2;
-            const uint32_t t = trow + (uint32_t)(i2 / E);
-            const int p = prow + (int)(i2 % E);
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t cc = u % nch, ab = u / nch, b = ab % I.t1, a = ab / I.t1;
+        const int64_t c0 = cc * CH;
+        const int nt = (int)(I.t2 - c0 < CH ? I.t2 - c0 : CH);
+        const size_t t0 = (size_t)I.base + (size_t)((a * I.t1 + b) * I.t2 + c0);
+        if ((int)threadIdx.x < nt) {
+            s_vis[threadIdx.x] = P.visit[t0 + threadIdx.x];
+            s_tf[threadIdx.x] = P.tflags[t0 + threadIdx.x];
+        }
+        __syncthreads();
+        for (int q0 = 0; q0 < NL; q0 += STAGE_BATCH) {
+            double v[STAGE_BATCH];
+#pragma unroll
+            for (int q = 0; q < STAGE_BATCH; q++) {
+                const int idx = (int)threadIdx.x + (q0 + q) * STAGE_THREADS;
+                const int k = idx / V;
+                v[q] = FMM_INF;
+                if (q0 + q < NL && k < nt && s_vis[k]) v[q] = P.Tt[t0 * V + idx];
+            }
+#pragma unroll
+            for (int q = 0; q < STAGE_BATCH; q++) {
+                const int idx = (int)threadIdx.x + (q0 + q) * STAGE_THREADS;
+                const int k = idx / V;
+                if (q0 + q < NL) buf[k * TS + (idx - k * V)] = v[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < NS; q++) {
+            const int idx = (int)threadIdx.x + q * STAGE_THREADS;
+            const int r = idx / W, c = idx - r * W, k = c / E;
+            const int64_t i0 = a * E + r / E, i1 = b * E + r % E, i2 = c0 * E + c;
+            if (k >= nt || i0 >= I.n0 || i1 >= I.n1 || i2 >= I.n2) continue;
+            const int p = r * E + c % E;
+            const double x = buf[k * TS + p];
             bool seed = false;
-            if (P.tflags[t] & TF_SEED) seed = (P.mask[(size_t)t * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
-            const double v = P.visit[t] ? P.Tt[(size_t)t * V + p] : FMM_INF;
-            const double a = fabs(v);
-            const uint8_t neg = v < 0.0 ? 0x80 : 0;
+            if (s_tf[k] & TF_SEED) seed = (P.mask[(t0 + k) * P.mask_words + (p >> 6)] >> (p & 63)) & 1ull;
+            const double ax = fabs(x);
+            const uint8_t neg = x < 0.0 ? 0x80 : 0;
             uint8_t st;
             double out = FMM_INF;
             if (seed) {
                 st = 3 | neg;
-                out = v;
-                mx = fmax(mx, a);
-            } else if (a < FMM_INF && a <= P.width) {
+                out = x;
+                mx = fmax(mx, ax);
+            } else if (ax < FMM_INF && ax <= P.width) {
                 st = 2 | neg;
-                out = v;
+                out = x;
                 acc++;
-                mx = fmax(mx, a);
-            } else if (a < FMM_INF) {
+                mx = fmax(mx, ax);
+            } else if (ax < FMM_INF) {
                 st = 1 | neg;
             } else {
                 st = 0;
             }
+            const int64_t g = (i0 * I.n1 + i1) * I.n2 + i2;
             I.T[g] = out;
             if (I.status) I.status[g] = st;
         }
+        __syncthreads();
     }
-    __shared__ unsigned long long s_acc[16];
-    __shared__ double s_mx[16];
+    __shared__ unsigned long long s_acc[STAGE_THREADS / 64];
+    __shared__ double s_mx[STAGE_THREADS / 64];
     acc = wave_sum(acc);
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1678,13 +1743,13 @@ template <int E> __global__ void k_finalize(Params P, Inst I, uint32_t j)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long a = 0;
+        unsigned long long sa = 0;
         double m = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); w++) {
-            a += s_acc[w];
+        for (int w = 0; w < STAGE_THREADS / 64; w++) {
+            sa += s_acc[w];
             m = fmax(m, s_mx[w]);
         }
-        if (a) atomicAdd(&P.ictl[j].n_accepted, a);
+        if (sa) atomicAdd(&P.ictl[j].n_accepted, sa);
         atomicMax(&P.ictl[j].max_abs_bits, bits_of(m));
     }
 }
@@ -1723,12 +1788,13 @@ template <int E> static hipError_t launch_prepare_t(const Params &P, const Inst 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int64_t j = 0; j < n; j++) {
         const Inst &I = insts[j];
-        const int64_t slabs = (int64_t)I.t0 * E * I.t1;
-        const unsigned tb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(slabs, (int64_t)cus * 8));
+        const int ch = f64 ? Stage<E, double>::CH : Stage<E, float>::CH;
+        const int64_t units = (int64_t)I.t0 * I.t1 * ((I.t2 + ch - 1) / ch);
+        const unsigned tb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * 8));
         if (f64)
-            hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(64 * E), 0, s, P, I, (uint32_t)j);
+            hipLaunchKernelGGL((k_tile_speed<E, double>), dim3(tb), dim3(STAGE_THREADS), 0, s, P, I, (uint32_t)j);
         else
-            hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(64 * E), 0, s, P, I, (uint32_t)j);
+            hipLaunchKernelGGL((k_tile_speed<E, float>), dim3(tb), dim3(STAGE_THREADS), 0, s, P, I, (uint32_t)j);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     bool any_seeds = false;
@@ -1836,9 +1902,9 @@ template <int E> static hipError_t launch_finalize_t(const Params &P, const Inst
     const int cus = num_cus();
     for (int64_t j = 0; j < n; j++) {
         const Inst &I = insts[j];
-        const int64_t slabs = I.n0 * I.t1;
-        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(slabs, (int64_t)cus * 8));
-        hipLaunchKernelGGL(k_finalize<E>, dim3(blocks), dim3(64 * E), 0, s, P, I, (uint32_t)j);
+        const int64_t units = (int64_t)I.t0 * I.t1 * ((I.t2 + Stage<E, double>::CH - 1) / Stage<E, double>::CH);
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(units, (int64_t)cus * 8));
+        hipLaunchKernelGGL(k_finalize<E>, dim3(blocks), dim3(STAGE_THREADS), 0, s, P, I, (uint32_t)j);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
