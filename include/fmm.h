@@ -42,8 +42,11 @@ typedef enum {
     FMM_EDEVICE = -5  /* device-detected input error (seeds, speed) or abort     */
 } fmm_status;
 
-/* Storage type of the speed array F (the arithmetic is FP64 either way). */
-typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
+/* Storage type of the speed array F (the arithmetic is FP64 either way).
+ * The last enumerator only widens the type's range to every int, so that an
+ * invalid value a caller passes is a defined value the library can reject
+ * (FMM_EINVAL) rather than undefined behaviour in C++. */
+typedef enum { FMM_F32 = 0, FMM_F64 = 1, FMM_DTYPE_RANGE_ = 0x7fffffff } fmm_dtype;
 
 /* Option flags. */
 #define FMM_VALIDATE 1u /* check on the device that every F value is finite */

@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# FMM_ORACLE_LIB selects another build of the same source (the sanitizer
+# test runs the oracle suite against an AddressSanitizer build this way)
+_LIB_PATH = os.environ.get("FMM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 ST_FAR, ST_BAND, ST_ACCEPTED, ST_SEED, ST_NEG = 0, 1, 2, 3, 0x80

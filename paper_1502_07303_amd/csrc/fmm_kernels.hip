@@ -31,6 +31,7 @@
 
 #include "fmm_device.h"
 #include "fmm_internal.h"
+#include "fmm_tile.h"
 
 namespace fmm {
 
@@ -43,18 +44,6 @@ __global__ void k_eval_godunov(const double *__restrict__ a, const double *__res
 
 // ---------------------------------------------------------------------------
 // Tile geometry, thread groups and per-tile LDS.
-
-template <int E> struct Geo {
-    static constexpr int D = E + 2;          // tile plus one-point halo per side
-    static constexpr int DV = D * D * D;
-    static constexpr int V = E * E * E;      // interior points
-    static constexpr int K = (V + 63) / 64;  // interior points per lane in a one-wavefront scan
-    static constexpr int FACE = E * E;
-    static constexpr int OX = D * D, OY = D, OZ = 1;
-    static constexpr int LOG = (E == 4) ? 2 : (E == 8) ? 3 : 4;
-    __device__ static constexpr int dom(int i0, int i1, int i2) { return ((i0 + 1) * D + (i1 + 1)) * D + (i2 + 1); }
-    __device__ static constexpr int domp(int p) { return dom(p >> (2 * LOG), (p >> LOG) & (E - 1), p & (E - 1)); }
-};
 
 // A tile is marched by a group of G threads: one wavefront (G = 64) for the
 // 4^3 and 8^3 tiles, several per workgroup; the whole workgroup of G / 64
@@ -75,27 +64,6 @@ template <int G> struct Grp {
             __syncthreads();
     }
 };
-
-// Coordinates of halo cell (face f, in-face position u, w): face f = 2*axis +
-// (1 for the + side); the in-face coordinates follow the other two axes in order.
-template <int E> __device__ __forceinline__ void face_cell(int f, int u, int w, int &c0, int &c1, int &c2)
-{
-    const int ax = f >> 1;
-    const int hc = (f & 1) ? E : -1;
-    c0 = ax == 0 ? hc : u;
-    c1 = ax == 0 ? u : (ax == 1 ? hc : w);
-    c2 = ax == 2 ? hc : w;
-}
-
-// The interior cell adjacent to a halo cell of face f.
-template <int E> __device__ __forceinline__ void face_inner(int f, int &c0, int &c1, int &c2)
-{
-    const int ax = f >> 1;
-    const int ic = (f & 1) ? E - 1 : 0;
-    if (ax == 0) c0 = ic;
-    else if (ax == 1) c1 = ic;
-    else c2 = ic;
-}
 
 // Wavefronts per workgroup of the 8^3-tile driver (one workgroup per CU; LDS
 // bounds it at 12 for FP32 speeds and 10 for FP64).
@@ -1478,24 +1446,6 @@ __global__ void k_init_ws(Params P, int E)
     const int64_t nm = (int64_t)P.ntiles * P.mask_words;
     for (int64_t i = i0; i < nm; i += stride) P.mask[i] = 0ull;
 }
-
-// LDS-staged conversion between a row-major grid and the tiled layout.  A
-// work unit is an E x E bundle of grid rows (one tile row along axes 0 and 1)
-// over a chunk of CH consecutive tiles along axis 2.  Those CH tiles are
-// consecutive in the tiled layout, so the tiled side of a unit is one
-// contiguous run of CH * V values and the row-major side is E * E row pieces
-// of CH * E contiguous values: both sides stream in long runs.  Tiles are E
-// values apart in LDS beyond their V values, which puts the E row pieces of a
-// wavefront's 64 consecutive columns in distinct banks.
-constexpr int STAGE_THREADS = 256;
-constexpr int STAGE_BATCH = 8;  // loads a thread keeps in flight
-template <int E, typename T> struct Stage {
-    static constexpr int V = E * E * E;
-    static constexpr int CH = E == 16 ? (sizeof(T) == 8 ? 2 : 4) : E == 8 ? (sizeof(T) == 8 ? 8 : 16) : 32;
-    static constexpr int W = CH * E;  // columns of a row piece
-    static constexpr int R = E * E;   // row pieces of a unit
-    static constexpr int TS = V + E;  // LDS stride of one tile
-};
 
 // Tiled copy of one problem's speeds (0 outside its grid) and the problem
 // index of each of its tiles.

@@ -14,7 +14,10 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfmm.so")
+# FMM_LIB selects another build of the same sources (the sanitizer test
+# runs the host-side ABI checks against a build whose host code carries
+# AddressSanitizer this way)
+LIB_PATH = os.environ.get("FMM_LIB") or os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_EDEVICE = 0, -1, -2, -3, -4, -5
 FMM_F32, FMM_F64 = 0, 1
