@@ -91,7 +91,7 @@ def kernel_tag():
     counter summary to the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("fmm_kernels.hip", "fmm_internal.h", "fmm_device.h", "fmm_api.cpp"):
+    for f in ("fmm_kernels.hip", "fmm_internal.h", "fmm_device.h", "fmm_tile.h", "fmm_api.cpp"):
         with open(os.path.join(ROOT, "paper_1502_07303_amd", "csrc", f), encoding="utf-8") as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
