@@ -349,17 +349,7 @@ template <typename FT> static hipError_t launch_adjoint_t(const AdjParams &P, co
     const unsigned grid = (unsigned)(std::min(occ, FMM_ADJ_WG_PER_CU) * cus);
     AdjParams Pc = P;
     void *args[] = {&Pc};
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return e;
-    if (cs == hipStreamCaptureStatusActive) {
-        // a graph node: the grid is at most one occupancy wave and runs after
-        // its predecessors, so its workgroups are resident together
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(ADJ_BLOCK), 0, s, Pc);
-        e = hipGetLastError();
-    } else {
-        e = hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(ADJ_BLOCK), args, 0, s);
-    }
-    if (e != hipSuccess) return e;
+    if ((e = launch_coresident((const void *)kern, dim3(grid), dim3(ADJ_BLOCK), args, s)) != hipSuccess) return e;
     // gather each output array over the problems that share it
     std::vector<bool> done((size_t)n, false);
     for (int64_t j = 0; j < n; j++) {

@@ -1,9 +1,11 @@
-// Device helpers shared by the forward solver and the adjoint kernels.
+// Device helpers shared by the forward solver and the adjoint kernels, and
+// the launch of their persistent kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 namespace fmm {
 
@@ -193,6 +195,37 @@ __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t *abort, uint32
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host side, shared by the forward driver and the adjoint sweep.
+
+// Launch a persistent kernel whose workgroups must all be resident at once
+// (its device-wide barriers wait for every workgroup): a cooperative launch.
+// Stream capture records the launch as an ordinary kernel node, so the
+// cooperative attribute is set on the node the launch just added (the
+// stream's only capture dependency), and a replay of the graph keeps the
+// guarantee.
+inline hipError_t launch_coresident(const void *kern, dim3 grid, dim3 block, void **args, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    if ((e = hipLaunchCooperativeKernel(kern, grid, block, args, 0, s)) != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusActive) return hipSuccess;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    hipGraph_t g = nullptr;
+    unsigned long long id = 0;
+    if ((e = hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &nd)) != hipSuccess) return e;
+    if (nd != 1 || !deps) return hipErrorStreamCaptureUnsupported;
+    hipGraphNodeType ty = hipGraphNodeTypeEmpty;
+    if ((e = hipGraphNodeGetType(deps[0], &ty)) != hipSuccess) return e;
+    if (ty != hipGraphNodeTypeKernel) return hipErrorStreamCaptureUnsupported;
+    hipLaunchAttributeValue v;
+    memset(&v, 0, sizeof v);
+    v.cooperative = 1;
+    return hipGraphKernelNodeSetAttribute(deps[0], hipLaunchAttributeCooperative, &v);
 }
 
 }  // namespace fmm

@@ -1806,18 +1806,10 @@ static hipError_t launch_driver_t(const Params &P, hipStream_t s, uint32_t *nwg_
     Params Pc = P;
     void *args[] = {&Pc};
     if (nwg_out) *nwg_out = grid;
-    // Under stream capture (a HIP graph) the launch is an ordinary kernel
-    // node: the grid is sized to one full occupancy wave, every predecessor
-    // in the stream has finished, so all workgroups are resident together.
-    // Should they not be, the barrier's bounded wait aborts the solve.
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(s, &cs);
-    if (e != hipSuccess) return e;
-    if (cs == hipStreamCaptureStatusActive) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(NW * 64), 0, s, Pc);
-        return hipGetLastError();
-    }
-    return hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(NW * 64), args, 0, s);
+    // one full occupancy wave, launched cooperatively (also under stream
+    // capture); should the workgroups still not be resident together, the
+    // barrier's bounded wait aborts the solve
+    return launch_coresident((const void *)kern, dim3(grid), dim3(NW * 64), args, s);
 }
 
 // The weighted local solver (per-axis spacing) is a separate instantiation,
