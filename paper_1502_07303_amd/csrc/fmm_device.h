@@ -12,6 +12,46 @@ namespace fmm {
 #define FMM_INF __builtin_huge_val()
 
 // ---------------------------------------------------------------------------
+// Correctly rounded square root and division by 3 for the local solver, in
+// fewer instructions than the general library sequences.
+//
+// solver_sqrt: the hardware reciprocal square root estimate y ~ 1/sqrt(x),
+// one coupled Newton step on s ~ sqrt(x) and h ~ 1/(2 sqrt(x)) (Goldschmidt's
+// iteration), then two residual corrections s += (x - s^2) h; the last one
+// rounds correctly.  The general routine additionally rescales tiny inputs
+// and patches 0 and +inf.  Here inputs below 2^-767 (0 included) take the
+// library routine on a branch that the solver's discriminants practically
+// never reach; +inf (only when r = +inf, where the solver returns +inf from
+// its first root) gives NaN, which the root comparisons reject.
+__device__ __forceinline__ double solver_sqrt(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = y * 0.5;
+    const double e = __builtin_fma(-h, s, 0.5);
+    s = __builtin_fma(s, e, s);
+    h = __builtin_fma(h, e, h);
+    double d = __builtin_fma(-s, s, x);
+    s = __builtin_fma(d, h, s);
+    d = __builtin_fma(-s, s, x);
+    s = __builtin_fma(d, h, s);
+    if (__builtin_expect(x < 0x1p-767, 0)) {
+        asm volatile("");  // keeps the rare path a branch (not computed and selected)
+        s = sqrt(x);
+    }
+    return s;
+}
+
+// x / 3, correctly rounded: q = x * RN(1/3) is within one ulp, and one
+// remainder step q + (x - 3 q) RN(1/3) rounds correctly (Markstein's
+// theorem; x / 3 is never a tie).
+__device__ __forceinline__ double div3(double x)
+{
+    const double third = 1.0 / 3.0;
+    const double q = x * third;
+    return __builtin_fma(__builtin_fma(-q, 3.0, x), third, q);
+}
+
+// ---------------------------------------------------------------------------
 // Local solver (Alg. 11 with Eqs. 4-7).  a = per-axis upwind values (+inf when
 // an axis has no upwind neighbour), r = h / F.  With a1 <= a2 <= a3:
 //   u1 = a1 + r
@@ -36,7 +76,7 @@ __device__ __forceinline__ double godunov_sel(double x, double y, double z, doub
         double d12 = a2 - a1;
         double D2 = 2.0 * r2 - d12 * d12;
         if (D2 >= 0.0) {
-            double u2 = ((a1 + a2) + sqrt(D2)) * 0.5;
+            double u2 = ((a1 + a2) + solver_sqrt(D2)) * 0.5;
             if (u2 > a2 && u2 < best) {
                 best = u2;
                 *k = 2;
@@ -46,7 +86,7 @@ __device__ __forceinline__ double godunov_sel(double x, double y, double z, doub
             double d13 = a3 - a1, d23 = a3 - a2;
             double D3 = 3.0 * r2 - ((d12 * d12 + d13 * d13) + d23 * d23);
             if (D3 >= 0.0) {
-                double u3 = (((a1 + a2) + a3) + sqrt(D3)) / 3.0;
+                double u3 = div3(((a1 + a2) + a3) + solver_sqrt(D3));
                 if (u3 > a3 && u3 < best) {
                     best = u3;
                     *k = 3;

@@ -94,6 +94,39 @@ def test_device_local_solver_bitwise(fmm, oracle_mod):
     assert np.array_equal(got.view(np.uint64), expect.view(np.uint64))
 
 
+def test_device_local_solver_bitwise_edges(fmm, oracle_mod):
+    """Device G against the oracle's G where the square roots and the division
+    by 3 leave their usual range: discriminants that are exactly zero, tiny or
+    subnormal, r = 0 and r = +inf (a zero speed), equal upwind values, and
+    values near the top of the double range."""
+    rng = np.random.default_rng(1)
+    rows, rs = [], []
+    # D2 = 2 r^2 - (a2 - a1)^2 exactly zero: a1 = 0, a2 = d with RN(d d) = RN(2 r r)
+    for r in rng.uniform(1e-3, 10.0, size=20000):
+        d0 = r * math.sqrt(2.0)
+        for k in range(-3, 4):
+            d = d0 + k * math.ulp(d0)
+            if d * d == 2.0 * r * r:
+                rows.append((0.0, d, math.inf))
+                rs.append(r)
+                rows.append((0.0, d, d))
+                rs.append(r)
+    assert len(rows) > 10
+    for r in (0.0, 1e-300, 1e-200, 1e-160, 1e-155, 1e-120, 1e-100, 5e-324, math.inf, 1e150):
+        for base in (0.0, 1e-300, 1e-160, 1.0, 1e150):
+            for spread in (0.0, 0.5, 1.0, 2.0):
+                d = spread * (r if math.isfinite(r) else 1.0)
+                rows += [(base, base, base), (base, base + d, base + 2 * d), (base, base + d, math.inf),
+                         (base, math.inf, math.inf), (base + d, base, base + 0.5 * d)]
+                rs += [r] * 5
+    a = np.array(rows, dtype=np.float64)
+    r = np.array(rs, dtype=np.float64)
+    expect = oracle_mod.godunov_batch(a, r)
+    got = fmm.eval_godunov(torch.from_numpy(a).cuda(), torch.from_numpy(r).cuda()).cpu().numpy()
+    bad = np.nonzero(got.view(np.uint64) != expect.view(np.uint64))[0]
+    assert bad.size == 0, [(a[i].tolist(), r[i], got[i], expect[i]) for i in bad[:5]]
+
+
 def test_single_tile_infinite_stride_two_restarts(fmm, oracle_mod):
     """Sec. 5.3: one subdomain with an infinite stride finishes in 2 restarts."""
     (row,) = load_golden("restarts_single_subdomain.txt")
