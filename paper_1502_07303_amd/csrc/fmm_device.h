@@ -51,6 +51,21 @@ __device__ __forceinline__ double div3(double x)
     return __builtin_fma(__builtin_fma(-q, 3.0, x), third, q);
 }
 
+// h / f for the march's r = h / F: a reciprocal estimate refined by two
+// Newton steps, the quotient, and one remainder correction.  For operands of
+// moderate exponents this is the correctly rounded quotient (the general
+// routine additionally rescales extreme exponents and patches special
+// values).  A zero speed (seeds and impassable cells) gives NaN: no root
+// comparison accepts it, so the cell keeps its value, as with r = +inf.
+__device__ __forceinline__ double solver_div(double h, double f)
+{
+    double y = __builtin_amdgcn_rcp(f);
+    y = __builtin_fma(y, __builtin_fma(-f, y, 1.0), y);
+    y = __builtin_fma(y, __builtin_fma(-f, y, 1.0), y);
+    const double q = h * y;
+    return __builtin_fma(__builtin_fma(-f, q, h), y, q);
+}
+
 // ---------------------------------------------------------------------------
 // Local solver (Alg. 11 with Eqs. 4-7).  a = per-axis upwind values (+inf when
 // an axis has no upwind neighbour), r = h / F.  With a1 <= a2 <= a3:

@@ -405,7 +405,7 @@ __device__ __forceinline__ double cell_r(const TileLds<E, FT, G> &L, int p, doub
     if constexpr (sizeof(FT) == 8)
         return L.F[p];
     else
-        return h / (double)L.F[p];
+        return solver_div(h, (double)L.F[p]);
 }
 
 // Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
@@ -1137,7 +1137,12 @@ __device__ __forceinline__ void run_phase(const Params &P, TileLds<E, FT, G> &L,
         uint32_t dbits = 0;
         double lastb[2] = {-FMM_INF, -FMM_INF};
         if (mode != MODE_INIT) {
-            if (rk == 0) dbits = atomicExch(&dcons[t], 0u);
+            // the word was last raised before the barrier that began this
+            // phase, and no other group handles tile t in this phase
+            if (rk == 0) {
+                dbits = dcons[t];
+                if (dbits) dcons[t] = 0u;
+            }
             const TileMeta m = P.meta[t];
             lastb[0] = m.lastb[0];
             lastb[1] = m.lastb[1];
@@ -1189,7 +1194,7 @@ __device__ __forceinline__ void run_phase(const Params &P, TileLds<E, FT, G> &L,
 #pragma unroll
                 for (int q = 0; q < 6; q++)
                     if ((uint32_t)(q >> 1) != phase % 3u && xb[q] != bits_of(FMM_INF))
-                        atomicExch(&tx[q], bits_of(FMM_INF));
+                        __hip_atomic_store(&tx[q], bits_of(FMM_INF), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             Grp<G>::sync();
         }
