@@ -55,8 +55,7 @@ __device__ __forceinline__ double div3(double x)
 // Newton steps, the quotient, and one remainder correction.  For operands of
 // moderate exponents this is the correctly rounded quotient (the general
 // routine additionally rescales extreme exponents and patches special
-// values).  A zero speed (seeds and impassable cells) gives NaN: no root
-// comparison accepts it, so the cell keeps its value, as with r = +inf.
+// values).  f must be positive and finite.
 __device__ __forceinline__ double solver_div(double h, double f)
 {
     double y = __builtin_amdgcn_rcp(f);
@@ -82,11 +81,11 @@ __device__ __forceinline__ double godunov_sel(double x, double y, double z, doub
     double lo = fmin(x, y), hi = fmax(x, y);
     double a3 = fmax(hi, z), m = fmin(hi, z);
     double a1 = fmin(lo, m), a2 = fmax(lo, m);
-    *k = 0;
-    if (!(a1 < FMM_INF)) return FMM_INF;
+    // no upwind value: a1 = +inf makes the first root +inf (r >= 0), with
+    // no branch ahead of the one on a2
+    *k = a1 < FMM_INF ? 1 : 0;
     double r2 = r * r;
     double best = a1 + r;
-    *k = 1;
     if (a2 < FMM_INF) {
         double d12 = a2 - a1;
         double D2 = 2.0 * r2 - d12 * d12;

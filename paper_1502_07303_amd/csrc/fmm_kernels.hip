@@ -402,10 +402,13 @@ __device__ __forceinline__ bool is_source(double v, uint8_t fl, const double bnd
 template <int E, typename FT, int G>
 __device__ __forceinline__ double cell_r(const TileLds<E, FT, G> &L, int p, double h)
 {
-    if constexpr (sizeof(FT) == 8)
+    if constexpr (sizeof(FT) == 8) {
         return L.F[p];
-    else
-        return solver_div(h, (double)L.F[p]);
+    } else {
+        // fixed cells (seeds, impassable cells) hold speed 0
+        const float f = L.F[p];
+        return f > 0.0f ? solver_div(h, (double)f) : FMM_INF;
+    }
 }
 
 // Evaluate Solve_Quadratic_Parallel at interior point p: returns true and the
@@ -431,16 +434,19 @@ __device__ __forceinline__ bool eval_point(const TileLds<E, FT, G> &L, const Spa
     const int d = Gm::domp(p);
     vp = L.T[d];
     if constexpr (!TWO) {
+        // the neighbours are read first and the speed right after them, so
+        // that all reads share one LDS round trip
         double m[3];
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
             const int off = ax == 0 ? Gm::OX : ax == 1 ? Gm::OY : Gm::OZ;
             na[2 * ax] = L.T[d - off];
             na[2 * ax + 1] = L.T[d + off];
-            m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
         }
-        // no finite neighbour: the solver returns +inf, which never beats vp
         const double r = cell_r(L, p, h);
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) m[ax] = fmin(na[2 * ax], na[2 * ax + 1]);
+        // no finite neighbour: the solver returns +inf, which never beats vp
         int kk;
         const double u = AN ? godunov_w_sel(m[0], m[1], m[2], sp.s[0], sp.s[1], sp.s[2], r, &kk)
                             : godunov_sel(m[0], m[1], m[2], r, &kk);
@@ -968,27 +974,30 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
             }
         }
         const bool self = lane == 6 && (tm0 < FMM_INF || tm1 < FMM_INF);
-        bool toD = false, live = self;
         if (self) u = t;
-        if (have && src) {
-            // a new source value crossed the face: the neighbour re-marches
-            const uint32_t old = atomicOr(&dprod[u], 1u << (lane ^ 1));
-            if (old == 0) {
-                if (second)
-                    toD = true;
-                else
-                    live = true;
-            }
-        } else if (have) {
-            // only band values: they join the neighbour's pending minimum
+        // a face with only band values: they join the neighbour's pending
+        // minimum, and the neighbour joins the next live list
+        const bool band = have && !src;
+        if (band) {
             const unsigned long long b0 = L.bm[lane * 2], b1 = L.bm[lane * 2 + 1];
             unsigned long long *ux = P.text + ((size_t)u * 3 + phase % 3u) * 2;
             if (b0 != bits_of(FMM_INF)) atomicMin(&ux[0], b0);
             if (b1 != bits_of(FMM_INF)) atomicMin(&ux[1], b1);
-            live = true;
         }
+        // a new source value crossed the face: the neighbour re-marches.  The
+        // dirty word and the live-list tag are requested together.
+        uint32_t old = 1;
+        if (have && src) old = atomicOr(&dprod[u], 1u << (lane ^ 1));
         bool append = false;
-        if (live) append = atomicExch(&P.epoch[u], epoch) != epoch;
+        if (self || band) append = atomicExch(&P.epoch[u], epoch) != epoch;
+        bool toD = false;
+        if (have && src && old == 0) {
+            if (second)
+                toD = true;
+            else
+                append = atomicExch(&P.epoch[u], epoch) != epoch;
+        }
+        const bool live = self || band || (have && src && old == 0 && !second);
         // wave-uniform follow-up
         const unsigned long long mD = __ballot(toD), mL = __ballot(append);
         const unsigned long long mP = __ballot(have && src && live);
