@@ -570,43 +570,71 @@ __device__ __forceinline__ int relax(const Params &P, TileLds<E, FT, G> &L, doub
 
 // Smallest pending band value per side above level th: interior band values,
 // and halo values next to an interior cell that is not yet a source (they
-// become sources of this tile later).  Group-uniform result.
+// become sources of this tile later).  Group-uniform result.  The reads of
+// up to eight cells per thread are issued before any of them is used, so a
+// pass waits for one LDS round trip instead of one per cell.
 template <int E, typename FT, int G>
 __device__ __forceinline__ void band_min(TileLds<E, FT, G> &L, const double th[2], double &m0, double &m1)
 {
     using Gm = Geo<E>;
     constexpr int V = Gm::V, FACE = Gm::FACE;
+    constexpr int NI = V / G, NF = (6 * FACE + G - 1) / G;
+    constexpr int BI = NI < 8 ? NI : 8, BF = NF < 8 ? NF : 8;
+    static_assert(V % G == 0, "interior cells per thread");
     const int r = Grp<G>::rank();
     double a0 = FMM_INF, a1 = FMM_INF;
-    for (int p = r; p < V; p += G) {
-        const int d = Gm::domp(p);
-        if (!(L.fl[d] & FL_UPD)) continue;
-        const double v = L.T[d];
-        const double a = fabs(v);
-        if (a < FMM_INF) {
-            if (v < 0.0) {
-                if (a > th[0]) a0 = fmin(a0, a);
-            } else if (a > th[1]) {
-                a1 = fmin(a1, a);
+    for (int j0 = 0; j0 < NI; j0 += BI) {
+        double v[BI];
+        uint8_t f[BI];
+#pragma unroll
+        for (int j = 0; j < BI; j++) {
+            const int d = Gm::domp(r + G * (j0 + j));
+            f[j] = L.fl[d];
+            v[j] = L.T[d];
+        }
+#pragma unroll
+        for (int j = 0; j < BI; j++) {
+            if (!(f[j] & FL_UPD)) continue;
+            const double a = fabs(v[j]);
+            if (a < FMM_INF) {
+                if (v[j] < 0.0) {
+                    if (a > th[0]) a0 = fmin(a0, a);
+                } else if (a > th[1]) {
+                    a1 = fmin(a1, a);
+                }
             }
         }
     }
-    for (int q = r; q < 6 * FACE; q += G) {
-        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-        int c0, c1, c2;
-        face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = Gm::dom(c0, c1, c2);
-        const double v = L.T[d];
-        const double a = fabs(v);
-        if (!(a < FMM_INF) || (L.fl[d] & FL_SEED)) continue;
-        if (a <= (v < 0.0 ? th[0] : th[1])) continue;
-        face_inner<E>(f, c0, c1, c2);
-        const int di = Gm::dom(c0, c1, c2);
-        if (!(L.fl[di] & FL_UPD) || (L.fl[di] & FL_SRC)) continue;
-        if (v < 0.0)
-            a0 = fmin(a0, a);
-        else
-            a1 = fmin(a1, a);
+    for (int j0 = 0; j0 < NF; j0 += BF) {
+        double v[BF];
+        uint8_t fh[BF], fi[BF];
+#pragma unroll
+        for (int j = 0; j < BF; j++) {
+            const int q = r + G * (j0 + j);
+            v[j] = FMM_INF;  // a thread past the last face cell takes nothing
+            fh[j] = fi[j] = 0;
+            if (q < 6 * FACE) {
+                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+                int c0, c1, c2;
+                face_cell<E>(f, u, w, c0, c1, c2);
+                const int d = Gm::dom(c0, c1, c2);
+                face_inner<E>(f, c0, c1, c2);
+                v[j] = L.T[d];
+                fh[j] = L.fl[d];
+                fi[j] = L.fl[Gm::dom(c0, c1, c2)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BF; j++) {
+            const double a = fabs(v[j]);
+            if (!(a < FMM_INF) || (fh[j] & FL_SEED)) continue;
+            if (a <= (v[j] < 0.0 ? th[0] : th[1])) continue;
+            if (!(fi[j] & FL_UPD) || (fi[j] & FL_SRC)) continue;
+            if (v[j] < 0.0)
+                a0 = fmin(a0, a);
+            else
+                a1 = fmin(a1, a);
+        }
     }
     grp_min2(L, a0, a1);
     m0 = a0;
@@ -614,37 +642,69 @@ __device__ __forceinline__ void band_min(TileLds<E, FT, G> &L, const double th[2
 }
 
 // Mark the candidates next to cells whose value lies in (lo, hi] of their
-// side: they become sources when the level rises from lo to hi.
+// side: they become sources when the level rises from lo to hi.  The first
+// reads of a pass are issued together, as in band_min.
 template <int E, typename FT, int G>
 __device__ __forceinline__ void mark_new_sources(TileLds<E, FT, G> &L, const double lo[2], const double hi[2])
 {
     using Gm = Geo<E>;
     constexpr int V = Gm::V, FACE = Gm::FACE;
+    constexpr int NI = V / G, NF = (6 * FACE + G - 1) / G;
+    constexpr int BI = NI < 8 ? NI : 8, BF = NF < 8 ? NF : 8;
     const int r = Grp<G>::rank();
-    for (int p = r; p < V; p += G) {
-        const int d = Gm::domp(p);
-        if (!(L.fl[d] & FL_UPD)) continue;
-        const double v = L.T[d];
-        const double a = fabs(v);
-        const int s = v < 0.0 ? 0 : 1;
-        if (a < FMM_INF && a > lo[s] && a <= hi[s]) {
-            L.fl[d] |= FL_SRC;
-            mark_nbrs(L, p, d, a);
+    for (int j0 = 0; j0 < NI; j0 += BI) {
+        double v[BI];
+        uint8_t f[BI];
+#pragma unroll
+        for (int j = 0; j < BI; j++) {
+            const int d = Gm::domp(r + G * (j0 + j));
+            f[j] = L.fl[d];
+            v[j] = L.T[d];
+        }
+#pragma unroll
+        for (int j = 0; j < BI; j++) {
+            const int p = r + G * (j0 + j);
+            const int d = Gm::domp(p);
+            if (!(f[j] & FL_UPD)) continue;
+            const double a = fabs(v[j]);
+            const int s = v[j] < 0.0 ? 0 : 1;
+            if (a < FMM_INF && a > lo[s] && a <= hi[s]) {
+                L.fl[d] = f[j] | FL_SRC;
+                mark_nbrs(L, p, d, a);
+            }
         }
     }
-    for (int q = r; q < 6 * FACE; q += G) {
-        const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-        int c0, c1, c2;
-        face_cell<E>(f, u, w, c0, c1, c2);
-        const int d = Gm::dom(c0, c1, c2);
-        const double v = L.T[d];
-        const double a = fabs(v);
-        const int s = v < 0.0 ? 0 : 1;
-        if (!(a < FMM_INF && a > lo[s] && a <= hi[s]) || (L.fl[d] & FL_SEED)) continue;
-        L.fl[d] |= FL_SRC;
-        face_inner<E>(f, c0, c1, c2);
-        const int di = Gm::dom(c0, c1, c2);
-        if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > a) mark_cand(L, true, (c0 * E + c1) * E + c2);
+    for (int j0 = 0; j0 < NF; j0 += BF) {
+        double v[BF];
+        uint8_t fh[BF];
+#pragma unroll
+        for (int j = 0; j < BF; j++) {
+            const int q = r + G * (j0 + j);
+            v[j] = FMM_INF;  // a thread past the last face cell takes nothing
+            fh[j] = 0;
+            if (q < 6 * FACE) {
+                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+                int c0, c1, c2;
+                face_cell<E>(f, u, w, c0, c1, c2);
+                const int d = Gm::dom(c0, c1, c2);
+                v[j] = L.T[d];
+                fh[j] = L.fl[d];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BF; j++) {
+            const double a = fabs(v[j]);
+            const int s = v[j] < 0.0 ? 0 : 1;
+            if (!(a < FMM_INF && a > lo[s] && a <= hi[s]) || (fh[j] & FL_SEED)) continue;
+            const int q = r + G * (j0 + j);
+            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            int c0, c1, c2;
+            face_cell<E>(f, u, w, c0, c1, c2);
+            L.fl[Gm::dom(c0, c1, c2)] = fh[j] | FL_SRC;
+            face_inner<E>(f, c0, c1, c2);
+            const int di = Gm::dom(c0, c1, c2);
+            if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > a) mark_cand(L, true, (c0 * E + c1) * E + c2);
+        }
     }
     Grp<G>::sync();
 }
