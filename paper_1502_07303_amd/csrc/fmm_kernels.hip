@@ -379,12 +379,19 @@ template <int E, typename FT, int G>
 __device__ __forceinline__ void mark_nbrs(TileLds<E, FT, G> &L, int p, int d, double a)
 {
     using Gm = Geo<E>;
-    if ((L.fl[d - Gm::OX] & FL_UPD) && fabs(L.T[d - Gm::OX]) > a) mark_cand(L, true, p - E * E);
-    if ((L.fl[d + Gm::OX] & FL_UPD) && fabs(L.T[d + Gm::OX]) > a) mark_cand(L, true, p + E * E);
-    if ((L.fl[d - Gm::OY] & FL_UPD) && fabs(L.T[d - Gm::OY]) > a) mark_cand(L, true, p - E);
-    if ((L.fl[d + Gm::OY] & FL_UPD) && fabs(L.T[d + Gm::OY]) > a) mark_cand(L, true, p + E);
-    if ((L.fl[d - Gm::OZ] & FL_UPD) && fabs(L.T[d - Gm::OZ]) > a) mark_cand(L, true, p - 1);
-    if ((L.fl[d + Gm::OZ] & FL_UPD) && fabs(L.T[d + Gm::OZ]) > a) mark_cand(L, true, p + 1);
+    // all twelve reads first (one LDS round trip); a halo neighbour never
+    // carries FL_UPD, so its out-of-interior index is never marked
+    const int od[6] = {-Gm::OX, Gm::OX, -Gm::OY, Gm::OY, -Gm::OZ, Gm::OZ};
+    const int op[6] = {-E * E, E * E, -E, E, -1, 1};
+    uint8_t f[6];
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        f[k] = L.fl[d + od[k]];
+        v[k] = L.T[d + od[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) mark_cand(L, (f[k] & FL_UPD) && fabs(v[k]) > a, p + op[k]);
 }
 
 // A domain cell is a source of the relaxation when it is a seed, or when its
@@ -899,17 +906,39 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
         // marks their neighbours when it reaches them (mark_new_sources), and
         // a band value never marks anything, so a cell gets a tentative value
         // only from an accepted neighbour, as in the sequential march.
-        for (int q = rk; q < 6 * FACE; q += G) {
-            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-            if (!((dbits >> f) & 1u)) continue;
-            int c0, c1, c2;
-            face_cell<E>(f, u, w, c0, c1, c2);
-            const int dh = Gm::dom(c0, c1, c2);
-            if (!(L.fl[dh] & FL_SRC)) continue;
-            const double vh = fabs(L.T[dh]);
-            face_inner<E>(f, c0, c1, c2);
-            const int di = Gm::dom(c0, c1, c2);
-            if ((L.fl[di] & FL_UPD) && fabs(L.T[di]) > vh) mark_cand(L, true, (c0 * E + c1) * E + c2);
+        // the reads of a thread's face cells are issued together
+        constexpr int NQ = (6 * FACE + G - 1) / G, BQ = NQ < 8 ? NQ : 8;
+        for (int j0 = 0; j0 < NQ; j0 += BQ) {
+            uint8_t fh[BQ], fi[BQ];
+            double vh[BQ], vi[BQ];
+#pragma unroll
+            for (int j = 0; j < BQ; j++) {
+                const int q = rk + G * (j0 + j);
+                fh[j] = fi[j] = 0;
+                vh[j] = vi[j] = FMM_INF;
+                if (q >= 6 * FACE) continue;
+                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+                if (!((dbits >> f) & 1u)) continue;
+                int c0, c1, c2;
+                face_cell<E>(f, u, w, c0, c1, c2);
+                const int dh = Gm::dom(c0, c1, c2);
+                face_inner<E>(f, c0, c1, c2);
+                const int di = Gm::dom(c0, c1, c2);
+                fh[j] = L.fl[dh];
+                vh[j] = L.T[dh];
+                fi[j] = L.fl[di];
+                vi[j] = L.T[di];
+            }
+#pragma unroll
+            for (int j = 0; j < BQ; j++) {
+                if (!(fh[j] & FL_SRC) || !(fi[j] & FL_UPD) || !(fabs(vi[j]) > fabs(vh[j]))) continue;
+                const int q = rk + G * (j0 + j);
+                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+                int c0, c1, c2;
+                face_cell<E>(f, u, w, c0, c1, c2);
+                face_inner<E>(f, c0, c1, c2);
+                mark_cand(L, true, (c0 * E + c1) * E + c2);
+            }
         }
     }
     Grp<G>::sync();
