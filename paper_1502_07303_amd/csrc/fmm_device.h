@@ -220,12 +220,17 @@ __device__ __forceinline__ unsigned long long ld_acq64(unsigned long long *p)
 // acquire fences, and a bounded wait.  A timeout (20 s) or an abort raised
 // elsewhere sets `abort` (and `timeout_bit` in *err), so every workgroup
 // leaves and the kernel always terminates.  Returns false on abort.
+// The workgroup barrier first orders every wavefront's writes before thread
+// 0's agent-scope release, which publishes them (release is cumulative), and
+// thread 0's acquire, which invalidates the CU's and the XCD's caches, comes
+// before the barrier that lets the other wavefronts read: one cache
+// write-back and one invalidation per workgroup instead of one per wavefront.
 __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t *abort, uint32_t *err, uint32_t timeout_bit,
                                           uint32_t &gen, uint32_t nwg, uint32_t *s_ok)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         gen++;
         uint32_t target = gen * nwg;
         uint32_t ok = 1;
@@ -244,10 +249,10 @@ __device__ __forceinline__ bool grid_sync(uint32_t *bar, uint32_t *abort, uint32
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_ok = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *s_ok != 0;
 }
 
