@@ -768,13 +768,14 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
     // axis-2 faces come from the neighbour's face buffer; +inf outside the
     // grid or for a tile not yet written in an earlier phase.
     constexpr int NI = (V + G - 1) / G, NF = (6 * FACE + G - 1) / G;
-    constexpr int CI = NI < 8 ? NI : 8, CF = NF < 8 ? NF : 8;
+    constexpr int CI = NI < 8 ? NI : 8;
+    static_assert(NF <= 8, "face-halo cells per thread");
     // the level the march starts at (the sources it loads)
     const double th0[2] = {mode == MODE_INIT ? -1.0 : lastb[0], mode == MODE_INIT ? -1.0 : lastb[1]};
     bool anyneg = false;  // a negative value in the tile or its halo
-    for (int j0 = 0; j0 < NI; j0 += CI) {
-        double vi[CI];
-        FT fi[CI];
+    double vi[CI];
+    FT fi[CI];
+    auto load_interior = [&](int j0) {
 #pragma unroll
         for (int j = 0; j < CI; j++) {
             const int p = rk + G * (j0 + j);
@@ -783,6 +784,8 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
                 fi[j] = Ft[tbase + p];
             }
         }
+    };
+    auto store_interior = [&](int j0) {
 #pragma unroll
         for (int j = 0; j < CI; j++) {
             const int p = rk + G * (j0 + j);
@@ -807,64 +810,73 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
                 if constexpr (!TileLds<E, FT, G>::BITS) L.cf[p] = 0;
             }
         }
-    }
-    for (int j0 = 0; j0 < NF; j0 += CF) {
-        double vh[CF];
-        uint32_t vis_h[CF], tf_h[CF];
+    };
+    // the first interior chunk and every face-halo read are issued before
+    // any of them is used.  The halo reads take no branch: a face on the
+    // grid boundary reads the tile's own cells (a valid address) and its
+    // stamp counts as "never written", so the cells come out +inf.
+    load_interior(0);
+    double vh[NF];
+    uint32_t vis_h[NF], tf_h[NF];
 #pragma unroll
-        for (int j = 0; j < CF; j++) {
-            const int q = rk + G * (j0 + j);
-            vis_h[j] = 0;
-            tf_h[j] = 0;
-            if (q < 6 * FACE) {
-                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-                const int ax = f >> 1;
-                const bool plus = f & 1;
-                int c0, c1, c2;
-                face_cell<E>(f, u, w, c0, c1, c2);
-                const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
-                const int32_t tna = ax == 0 ? G0.t0 : ax == 1 ? G0.t1 : G0.t2;
-                if (plus ? tca + 1 < tna : tca > 0) {
-                    const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
-                    const uint32_t tnb = plus ? t + ts : t - ts;
-                    const int n0c = ax == 0 ? (plus ? 0 : E - 1) : c0;
-                    const int n1c = ax == 1 ? (plus ? 0 : E - 1) : c1;
-                    const int n2c = ax == 2 ? (plus ? 0 : E - 1) : c2;
-                    vis_h[j] = P.visit[tnb];
-                    tf_h[j] = P.tflags[tnb];
-                    vh[j] = ax == 2 ? P.Zf[((size_t)tnb * 2 + (plus ? 0 : 1)) * FACE + n0c * E + n1c]
-                                    : Tt[(size_t)tnb * V + (n0c * E + n1c) * E + n2c];
-                }
-            }
+    for (int j = 0; j < NF; j++) {
+        const int q = rk + G * j;
+        vis_h[j] = 0;
+        tf_h[j] = 0;
+        if (q < 6 * FACE) {
+            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            const int ax = f >> 1;
+            const bool plus = f & 1;
+            int c0, c1, c2;
+            face_cell<E>(f, u, w, c0, c1, c2);
+            const int32_t tca = ax == 0 ? tx : ax == 1 ? ty : tz;
+            const int32_t tna = ax == 0 ? G0.t0 : ax == 1 ? G0.t1 : G0.t2;
+            const bool inside = plus ? tca + 1 < tna : tca > 0;
+            const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+            const uint32_t tnb = inside ? (plus ? t + ts : t - ts) : t;
+            const int n0c = ax == 0 ? (plus ? 0 : E - 1) : c0;
+            const int n1c = ax == 1 ? (plus ? 0 : E - 1) : c1;
+            const int n2c = ax == 2 ? (plus ? 0 : E - 1) : c2;
+            const uint32_t vs = P.visit[tnb];
+            const uint32_t tf = P.tflags[tnb];
+            vh[j] = ax == 2 ? P.Zf[((size_t)tnb * 2 + (plus ? 0 : 1)) * FACE + n0c * E + n1c]
+                            : Tt[(size_t)tnb * V + (n0c * E + n1c) * E + n2c];
+            vis_h[j] = inside ? vs : 0u;
+            tf_h[j] = inside ? tf : 0u;
         }
+    }
+    store_interior(0);
+    for (int j0 = CI; j0 < NI; j0 += CI) {
+        load_interior(j0);
+        store_interior(j0);
+    }
 #pragma unroll
-        for (int j = 0; j < CF; j++) {
-            const int q = rk + G * (j0 + j);
-            if (q < 6 * FACE) {
-                const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
-                const int ax = f >> 1;
-                const bool plus = f & 1;
-                int c0, c1, c2;
-                face_cell<E>(f, u, w, c0, c1, c2);
-                double v = FMM_INF;
-                uint8_t fl = 0;
-                if (vis_h[j] != 0 && vis_h[j] <= phase) v = vh[j];
-                if (tf_h[j] & TF_SEED) {
-                    // rare: the neighbour holds seeds; fetch its seed bit
-                    const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
-                    const uint32_t tnb = plus ? t + ts : t - ts;
-                    const int n0c = ax == 0 ? (plus ? 0 : E - 1) : c0;
-                    const int n1c = ax == 1 ? (plus ? 0 : E - 1) : c1;
-                    const int n2c = ax == 2 ? (plus ? 0 : E - 1) : c2;
-                    const int pn = (n0c * E + n1c) * E + n2c;
-                    if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
-                }
-                const int d = Gm::dom(c0, c1, c2);
-                if (is_source(v, fl, th0)) fl |= FL_SRC;
-                anyneg |= v < 0.0;
-                L.T[d] = v;
-                L.fl[d] = fl;
+    for (int j = 0; j < NF; j++) {
+        const int q = rk + G * j;
+        if (q < 6 * FACE) {
+            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            const int ax = f >> 1;
+            const bool plus = f & 1;
+            int c0, c1, c2;
+            face_cell<E>(f, u, w, c0, c1, c2);
+            double v = FMM_INF;
+            uint8_t fl = 0;
+            if (vis_h[j] != 0 && vis_h[j] <= phase) v = vh[j];
+            if (tf_h[j] & TF_SEED) {
+                // rare: the neighbour holds seeds; fetch its seed bit
+                const uint32_t ts = ax == 0 ? tsx : ax == 1 ? tsy : 1u;
+                const uint32_t tnb = plus ? t + ts : t - ts;
+                const int n0c = ax == 0 ? (plus ? 0 : E - 1) : c0;
+                const int n1c = ax == 1 ? (plus ? 0 : E - 1) : c1;
+                const int n2c = ax == 2 ? (plus ? 0 : E - 1) : c2;
+                const int pn = (n0c * E + n1c) * E + n2c;
+                if ((P.mask[(size_t)tnb * P.mask_words + (pn >> 6)] >> (pn & 63)) & 1ull) fl = FL_SEED;
             }
+            const int d = Gm::dom(c0, c1, c2);
+            if (is_source(v, fl, th0)) fl |= FL_SRC;
+            anyneg |= v < 0.0;
+            L.T[d] = v;
+            L.fl[d] = fl;
         }
     }
     if constexpr (TileLds<E, FT, G>::BITS)
