@@ -743,20 +743,28 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
 {
     using Gm = Geo<E>;
     constexpr int V = Gm::V, FACE = Gm::FACE;
-    const int lane = threadIdx.x & 63;
-    const int rk = Grp<G>::rank();
+    // The thread's rank is made opaque to the optimiser here: the addresses
+    // and offsets derived from it are then formed per march instead of being
+    // hoisted out of the phase loop and kept (and spilled) for the whole
+    // kernel; a reload of a spilled address in the middle of the tile's loads
+    // would make the loads wait for one another.
+    int rk = Grp<G>::rank();
+    asm volatile("" : "+v"(rk));
+    rk &= G - 1;  // the optimiser keeps knowing rk < G
+    const int lane = G == 64 ? rk : (int)(threadIdx.x & 63);
     const bool lead = Grp<G>::wave() == 0;  // the group's first wavefront
     const FT *__restrict__ Ft = (const FT *)P.Ft;
     double *__restrict__ Tt = P.Tt;
 
-    // tile coordinates inside its problem; neighbours are t +- stride
+    // tile coordinates inside its problem; neighbours are t +- stride.  The
+    // divisions run on the vector unit; the results are uniform and are
+    // moved back to scalar registers, so that neighbour tiles and their base
+    // addresses stay scalar.
     const uint32_t tl = t - G0.base;
-    const int32_t tz = (int32_t)(tl % (uint32_t)G0.t2);
-    const int32_t ty = (int32_t)((tl / (uint32_t)G0.t2) % (uint32_t)G0.t1);
-    const int32_t tx = (int32_t)(tl / ((uint32_t)G0.t2 * (uint32_t)G0.t1));
+    const int32_t tz = (int32_t)__builtin_amdgcn_readfirstlane(tl % (uint32_t)G0.t2);
+    const int32_t ty = (int32_t)__builtin_amdgcn_readfirstlane((tl / (uint32_t)G0.t2) % (uint32_t)G0.t1);
+    const int32_t tx = (int32_t)__builtin_amdgcn_readfirstlane(tl / ((uint32_t)G0.t2 * (uint32_t)G0.t1));
     const uint32_t tsx = (uint32_t)G0.t1 * (uint32_t)G0.t2, tsy = (uint32_t)G0.t2;
-    const bool hasSeed = (P.tflags[t] & TF_SEED) != 0;
-    const bool fresh = P.visit[t] == 0;  // never written: every cell is +inf
     const unsigned long long *mask = P.mask + (size_t)t * P.mask_words;
     const size_t tbase = (size_t)t * V;
 
@@ -785,7 +793,7 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
             }
         }
     };
-    auto store_interior = [&](int j0) {
+    auto store_interior = [&](int j0, bool hasSeed, bool fresh) {
 #pragma unroll
         for (int j = 0; j < CI; j++) {
             const int p = rk + G * (j0 + j);
@@ -814,7 +822,9 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
     // the first interior chunk and every face-halo read are issued before
     // any of them is used.  The halo reads take no branch: a face on the
     // grid boundary reads the tile's own cells (a valid address) and its
-    // stamp counts as "never written", so the cells come out +inf.
+    // stamp counts as "never written", so the cells come out +inf.  With one
+    // face per group pass (E^2 = G) the face of pass j is j itself, so the
+    // neighbour tile and its base addresses are known per pass.
     load_interior(0);
     double vh[NF];
     uint32_t vis_h[NF], tf_h[NF];
@@ -824,7 +834,7 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
         vis_h[j] = 0;
         tf_h[j] = 0;
         if (q < 6 * FACE) {
-            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            const int f = FACE == G ? j : q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
             const int ax = f >> 1;
             const bool plus = f & 1;
             int c0, c1, c2;
@@ -845,16 +855,20 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
             tf_h[j] = inside ? tf : 0u;
         }
     }
-    store_interior(0);
+    // the tile's own flags and stamp are requested after its cells (their
+    // use must not hold back the cell reads)
+    const bool hasSeed = (P.tflags[t] & TF_SEED) != 0;
+    const bool fresh = P.visit[t] == 0;  // never written: every cell is +inf
+    store_interior(0, hasSeed, fresh);
     for (int j0 = CI; j0 < NI; j0 += CI) {
         load_interior(j0);
-        store_interior(j0);
+        store_interior(j0, hasSeed, fresh);
     }
 #pragma unroll
     for (int j = 0; j < NF; j++) {
         const int q = rk + G * j;
         if (q < 6 * FACE) {
-            const int f = q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
+            const int f = FACE == G ? j : q / FACE, uv = q - f * FACE, u = uv / E, w = uv - u * E;
             const int ax = f >> 1;
             const bool plus = f & 1;
             int c0, c1, c2;
