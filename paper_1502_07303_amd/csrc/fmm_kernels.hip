@@ -52,6 +52,16 @@ __global__ void k_eval_godunov(const double *__restrict__ a, const double *__res
 template <int G> struct Grp {
     static constexpr int NWV = G / 64;  // wavefronts in the group
     __device__ static __forceinline__ int rank() { return G == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x; }
+    // The rank made opaque to the optimiser (its range stays known): the
+    // offsets derived from it are then formed where they are used instead of
+    // being hoisted out of the phase loop and kept, and spilled, for the
+    // whole kernel.
+    __device__ static __forceinline__ int rank_here()
+    {
+        int r = rank();
+        asm volatile("" : "+v"(r));
+        return r & (G - 1);
+    }
     __device__ static __forceinline__ int wave()
     {
         return G == 64 ? 0 : (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -260,13 +270,13 @@ __device__ __forceinline__ void mark_cand(TileLds<E, FT, G> &L, bool on, int q)
 template <int E, typename FT, int G> __device__ __forceinline__ int compact(TileLds<E, FT, G> &L)
 {
     constexpr int K = Geo<E>::K;
-    const int lane = threadIdx.x & 63;
+    const int lane = Grp<G>::rank_here() & 63;
     uint16_t *out = L.list;
     uint32_t cnt = 0;
     if constexpr (G > 64) {
         constexpr int C = Geo<E>::V / G;
         static_assert(C >= 1 && C <= 32 && 32 % C == 0, "cells per thread must divide a word");
-        const int r = Grp<G>::rank(), wv = Grp<G>::wave();
+        const int r = Grp<G>::rank_here(), wv = Grp<G>::wave();
         const int word = (r * C) >> 5, sh = (r * C) & 31;
         const uint32_t wbits = L.cfw[word];
         uint32_t bits = C == 32 ? wbits : (wbits >> sh) & ((1u << (C & 31)) - 1u);
@@ -523,7 +533,7 @@ __device__ __forceinline__ int relax(const Params &P, TileLds<E, FT, G> &L, doub
                                      WaveState &ws)
 {
     using Gm = Geo<E>;
-    const int r = Grp<G>::rank();
+    const int r = Grp<G>::rank_here();
     int n = compact(L);
     int rounds = 0;
     while (n > 0) {
@@ -588,7 +598,7 @@ __device__ __forceinline__ void band_min(TileLds<E, FT, G> &L, const double th[2
     constexpr int NI = V / G, NF = (6 * FACE + G - 1) / G;
     constexpr int BI = NI < 8 ? NI : 8, BF = NF < 8 ? NF : 8;
     static_assert(V % G == 0, "interior cells per thread");
-    const int r = Grp<G>::rank();
+    const int r = Grp<G>::rank_here();
     double a0 = FMM_INF, a1 = FMM_INF;
     for (int j0 = 0; j0 < NI; j0 += BI) {
         double v[BI];
@@ -658,7 +668,7 @@ __device__ __forceinline__ void mark_new_sources(TileLds<E, FT, G> &L, const dou
     constexpr int V = Gm::V, FACE = Gm::FACE;
     constexpr int NI = V / G, NF = (6 * FACE + G - 1) / G;
     constexpr int BI = NI < 8 ? NI : 8, BF = NF < 8 ? NF : 8;
-    const int r = Grp<G>::rank();
+    const int r = Grp<G>::rank_here();
     for (int j0 = 0; j0 < NI; j0 += BI) {
         double v[BI];
         uint8_t f[BI];
@@ -743,14 +753,9 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
 {
     using Gm = Geo<E>;
     constexpr int V = Gm::V, FACE = Gm::FACE;
-    // The thread's rank is made opaque to the optimiser here: the addresses
-    // and offsets derived from it are then formed per march instead of being
-    // hoisted out of the phase loop and kept (and spilled) for the whole
-    // kernel; a reload of a spilled address in the middle of the tile's loads
-    // would make the loads wait for one another.
-    int rk = Grp<G>::rank();
-    asm volatile("" : "+v"(rk));
-    rk &= G - 1;  // the optimiser keeps knowing rk < G
+    // The lane offsets are formed per march (a reload of a spilled address
+    // among the tile's loads would make them wait for one another).
+    const int rk = Grp<G>::rank_here();
     const int lane = G == 64 ? rk : (int)(threadIdx.x & 63);
     const bool lead = Grp<G>::wave() == 0;  // the group's first wavefront
     const FT *__restrict__ Ft = (const FT *)P.Ft;
