@@ -1010,15 +1010,30 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
 #ifdef FMM_PROFILE
     bool any_chg = false;
 #endif
-    for (int p = rk; p < V; p += G) {
+    // the flags and values of a thread's cells are read together (one LDS
+    // round trip); the changed-cell flags are kept as a bit mask
+    constexpr int NW = V / G;
+    static_assert(NW <= 32, "cells per thread");
+    double vw[NW];
+    uint32_t chgm = 0;
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        const int d = Gm::domp(rk + G * j);
+        const uint8_t fj = L.fl[d];
+        vw[j] = L.T[d];
+        chgm |= (uint32_t)((fj >> 2) & 1u) << j;  // FL_CHG
+    }
+#pragma unroll
+    for (int j = 0; j < NW; j++) {
+        const int p = rk + G * j;
         const int d = Gm::domp(p);
-        const bool chg = (L.fl[d] & FL_CHG) != 0;
+        const bool chg = (chgm >> j) & 1u;
 #ifdef FMM_PROFILE
         any_chg |= chg;
 #endif
         if (!(chg || fresh)) continue;
         const int i0 = p >> (2 * Gm::LOG), i1 = (p >> Gm::LOG) & (E - 1), i2 = p & (E - 1);
-        const double v = L.T[d];
+        const double v = vw[j];
         Tt[tbase + p] = v;
         if (i2 == 0) P.Zf[((size_t)t * 2 + 0) * FACE + i0 * E + i1] = v;
         if (i2 == E - 1) P.Zf[((size_t)t * 2 + 1) * FACE + i0 * E + i1] = v;
