@@ -1282,11 +1282,9 @@ __device__ __forceinline__ void run_phase(const Params &P, TileLds<E, FT, G> &L,
         double lastb[2] = {-FMM_INF, -FMM_INF};
         if (mode != MODE_INIT) {
             // the word was last raised before the barrier that began this
-            // phase, and no other group handles tile t in this phase
-            if (rk == 0) {
-                dbits = dcons[t];
-                if (dbits) dcons[t] = 0u;
-            }
+            // phase, and no other group handles tile t in this phase.  It is
+            // read with the tile's record (one round trip) and cleared below.
+            dbits = dcons[t];
             const TileMeta m = P.meta[t];
             lastb[0] = m.lastb[0];
             lastb[1] = m.lastb[1];
@@ -1316,6 +1314,7 @@ __device__ __forceinline__ void run_phase(const Params &P, TileLds<E, FT, G> &L,
                 p1 = bitsd((unsigned long long)L.bc[4] | ((unsigned long long)L.bc[5] << 32));
                 __syncthreads();
             }
+            if (rk == 0 && dbits) dcons[t] = 0u;
             const bool due =
                 dbits != 0 || (p0 < FMM_INF && p0 <= iv.bnd[0]) || (p1 < FMM_INF && p1 <= iv.bnd[1]);
             if (!due) {
