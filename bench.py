@@ -398,7 +398,7 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--stride-h", type=float, default=None,
                     help="restart stride in units of h (inf allowed); default: swept by the library's autotuner")
-    ap.add_argument("--sweep", default="3,4,5", help="strides (units of h) the autotuner tries")
+    ap.add_argument("--sweep", default="3,3.5,4,4.5", help="strides (units of h) the autotuner tries")
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-crop", type=int, default=352)
@@ -462,7 +462,7 @@ def main():
         t0 = time.perf_counter()
         tb = fmm.BatchSolver([{"F": w.F, "h": w.h, "seed_idx": w.seed_idx, "seed_val": w.seed_val}],
                              tile_edge=args.tile, with_status=False)
-        ms = tb.tune(edges=(args.tile,), strides_h=cand, reps=1)
+        ms = tb.tune(edges=(args.tile,), strides_h=cand, reps=2)
         stride_h = float(tb.opts.stride_h)
         sweep = {f"{sh:g}h": round(v, 3) for (_, sh), v in ms.items()}
         del tb
