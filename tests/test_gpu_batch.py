@@ -60,7 +60,7 @@ def mixed_batch(dtype=torch.float64):
 
 
 @pytest.mark.parametrize("edge", [4, 8, 16])
-@pytest.mark.parametrize("stride_h", [0.5, 2.0, 3.0, 4.0, 5.0, math.inf])
+@pytest.mark.parametrize("stride_h", [0.5, 2.0, 3.0, 3.5, 4.0, 4.5, 5.0, math.inf])
 def test_batch_parity_mixed(fmm, oracle_mod, edge, stride_h):
     dev = torch.device("cuda:0")
     ws = mixed_batch()

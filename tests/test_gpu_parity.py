@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12
 # the paper's strides (Sec. 5.1) and the ones the benchmark's autotuner tries
-STRIDES_H = (0.5, 1.5, 2.0, 3.0, 4.0, 5.0, math.inf)
+STRIDES_H = (0.5, 1.5, 2.0, 3.0, 3.5, 4.0, 4.5, 5.0, math.inf)
 
 
 @pytest.fixture(scope="module")

@@ -37,7 +37,7 @@ def test_spacing_parity(fmm, oracle_mod, sc, edge, dtype):
         w = inputs.random_small(shape, n_sources=2, seed=seed, zero_frac=zero, dtype=dtype)
         F, idx, val = w.numpy()
         To, so, _, _ = oracle_mod.solve(F, w.h, idx, val, axis_scale=sc)
-        for stride_h in (0.5, 2.0, 3.0, 4.0, 5.0, math.inf):
+        for stride_h in (0.5, 2.0, 3.0, 3.5, 4.0, 4.5, 5.0, math.inf):
             T, st, _ = fmm.solve(w.F.to(dev), w.h, w.seed_idx.to(dev), w.seed_val.to(dev),
                                  stride=stride_h * w.h, tile_edge=edge, axis_scale=sc, time_limit_s=30)
             rep = parity_report(T.cpu().numpy(), st.cpu().numpy(), To, so)
