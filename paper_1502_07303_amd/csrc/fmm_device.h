@@ -55,7 +55,8 @@ __device__ __forceinline__ double div3(double x)
 // Newton steps, the quotient, and one remainder correction.  For operands of
 // moderate exponents this is the correctly rounded quotient (the general
 // routine additionally rescales extreme exponents and patches special
-// values).  f must be positive and finite.
+// values).  f must be positive and finite (the tile load keeps an infinite
+// FP32 speed as the largest finite one).
 __device__ __forceinline__ double solver_div(double h, double f)
 {
     double y = __builtin_amdgcn_rcp(f);

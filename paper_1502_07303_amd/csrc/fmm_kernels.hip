@@ -815,10 +815,14 @@ __device__ __forceinline__ void tile_march(const Params &P, TileLds<E, FT, G> &L
                 // An FP64 slot holds r = h / F itself, computed once per cell
                 // with the same expression as for FP32 speeds.
                 const bool fixed = seed || !((double)fi[j] > 0.0);
+                // An infinite FP32 speed (r = 0) is kept as the largest finite
+                // one: the march's division wants a finite divisor, and
+                // h / FLT_MAX is below the rounding of any value it is added to
+                // unless that value is itself below about 1e-26.
                 if constexpr (sizeof(FT) == 8)
                     L.F[p] = fixed ? FMM_INF : G0.h / (double)fi[j];
                 else
-                    L.F[p] = fixed ? (FT)0 : fi[j];
+                    L.F[p] = fixed ? (FT)0 : fminf(fi[j], 3.402823466e38f);
                 L.fl[d] = f8;
                 if constexpr (!TileLds<E, FT, G>::BITS) L.cf[p] = 0;
             }

@@ -162,6 +162,38 @@ def test_random_speed_parity(fmm, oracle_mod, edge, shape, seed, nsrc, dtype, ze
         assert_parity(Tg, sg, To, so)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_extreme_speeds_parity(fmm, oracle_mod, dtype):
+    """Speeds at the ends of their range: +inf (r = 0: a point takes its
+    smallest upwind value), the largest and the smallest normal FP32 values,
+    a subnormal FP32 value, and impassable points, mixed into a random grid."""
+    w = inputs.random_small((37, 29, 41), n_sources=3, seed=41, dtype=torch.float64, zero_frac=0.05)
+    F = w.F.numpy().copy()
+    rng = np.random.default_rng(5)
+    src = set(w.seed_idx.tolist())
+    extremes = [np.inf, 3.402823466e38, 1.1754944e-38, 1e-40, 1e30, 1e-30]
+    for k, v in enumerate(extremes):
+        cells = rng.choice(F.size, size=200, replace=False)
+        for c in cells:
+            if int(c) not in src:
+                F.reshape(-1)[c] = v
+    F = torch.from_numpy(F).to(dtype)
+    w = type(w)(w.name, F, w.h, w.seed_idx, w.seed_val, w.width, w.meta)
+    To, so, _ = oracle_solve(oracle_mod, w)
+    fin = np.isfinite(To)
+    # tiny speeds give values near 1e38 at their own points; the others stay
+    # of order 1, so the bar is relative per point (1e-12 of max(1, |T|))
+    big = np.abs(To) > 1e3
+    assert np.any(big) and np.any(fin & ~big)
+    for edge in (4, 8, 16):
+        for stride_h in (2.0, 3.5, math.inf):
+            Tg, sg, st = gpu_solve(fmm, w, stride=stride_h * w.h, tile_edge=edge)
+            assert np.array_equal(sg, so), (edge, stride_h, int(np.count_nonzero(sg != so)))
+            assert np.array_equal(np.isfinite(Tg), fin)
+            err = np.abs(Tg[fin] - To[fin]) / np.maximum(1.0, np.abs(To[fin]))
+            assert float(err.max()) <= TOL, (edge, stride_h, float(err.max()))
+
+
 @pytest.mark.parametrize("edge", [8, 16])
 def test_many_tiles_parity(fmm, oracle_mod, edge):
     """A grid of several hundred 16^3 (or thousands of 8^3) tiles with a
