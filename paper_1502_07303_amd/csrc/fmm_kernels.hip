@@ -142,7 +142,11 @@ struct WaveState {
     uint32_t pending;     // tiles newly dirtied for the next restart (first wavefront of the group)
     double gmin0, gmin1;  // running min of band minima
     unsigned long long n_march, n_round;  // group-uniform counters (first wavefront of the group)
-    unsigned long long n_solve, n_reopen;  // per-lane counters
+    // per-lane counters for the statistics only, 32-bit (cheaper to count in
+    // the relaxation loop).  They are widened when summed at the end; a lane
+    // would wrap only after 4.3e9 local solves, some 2e4 times what one lane
+    // makes on a 1024^3 grid.
+    uint32_t n_solve, n_reopen;
 };
 
 // ---------------------------------------------------------------------------
@@ -1516,7 +1520,8 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WP
         nitems = len;
     }
     // ---- statistics
-    const unsigned long long ns = wave_sum(ws.n_solve), nr = wave_sum(ws.n_reopen);
+    const unsigned long long ns = wave_sum((unsigned long long)ws.n_solve),
+                             nr = wave_sum((unsigned long long)ws.n_reopen);
 #ifdef FMM_PROFILE
     if (lane == 0)
         for (int k = 0; k < 16; k++) atomicAdd(&c->prof[k], ws.prof[k]);
