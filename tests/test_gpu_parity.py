@@ -98,7 +98,8 @@ def test_device_local_solver_bitwise_edges(fmm, oracle_mod):
     """Device G against the oracle's G where the square roots and the division
     by 3 leave their usual range: discriminants that are exactly zero, tiny or
     subnormal, r = 0 and r = +inf (a zero speed), equal upwind values, and
-    values near the top of the double range."""
+    values near the top of the double range, where 2 r^2, 3 r^2, the squared
+    differences or a root's numerator overflow."""
     rng = np.random.default_rng(1)
     rows, rs = [], []
     # D2 = 2 r^2 - (a2 - a1)^2 exactly zero: a1 = 0, a2 = d with RN(d d) = RN(2 r r)
@@ -112,8 +113,12 @@ def test_device_local_solver_bitwise_edges(fmm, oracle_mod):
                 rows.append((0.0, d, d))
                 rs.append(r)
     assert len(rows) > 10
-    for r in (0.0, 1e-300, 1e-200, 1e-160, 1e-155, 1e-120, 1e-100, 5e-324, math.inf, 1e150):
-        for base in (0.0, 1e-300, 1e-160, 1.0, 1e150):
+    # r near the square root of the largest double, where 2 r^2 or 3 r^2
+    # overflows, and values near the top of the range, where the sum of a
+    # third root's numerator or the squared differences overflow
+    for r in (0.0, 1e-300, 1e-200, 1e-160, 1e-155, 1e-120, 1e-100, 5e-324, math.inf, 1e150,
+              9e153, 1.1e154, 1.4e154, 1e200, 1e300):
+        for base in (0.0, 1e-300, 1e-160, 1.0, 1e150, 1e200, 5e307):
             for spread in (0.0, 0.5, 1.0, 2.0):
                 d = spread * (r if math.isfinite(r) else 1.0)
                 rows += [(base, base, base), (base, base + d, base + 2 * d), (base, base + d, math.inf),
@@ -166,12 +171,18 @@ def test_random_speed_parity(fmm, oracle_mod, edge, shape, seed, nsrc, dtype, ze
 def test_extreme_speeds_parity(fmm, oracle_mod, dtype):
     """Speeds at the ends of their range: +inf (r = 0: a point takes its
     smallest upwind value), the largest and the smallest normal FP32 values,
-    a subnormal FP32 value, and impassable points, mixed into a random grid."""
+    a subnormal FP32 value, speeds so small that squared values overflow, and
+    impassable points (zero, negative and NaN speeds), mixed into a random
+    grid."""
     w = inputs.random_small((37, 29, 41), n_sources=3, seed=41, dtype=torch.float64, zero_frac=0.05)
     F = w.F.numpy().copy()
     rng = np.random.default_rng(5)
     src = set(w.seed_idx.tolist())
-    extremes = [np.inf, 3.402823466e38, 1.1754944e-38, 1e-40, 1e30, 1e-30]
+    # NaN, zero and negative speeds are impassable (no FMM_VALIDATE here);
+    # 1e-300 and 1e-160 (FP64 only; 0 in FP32) give values whose squares
+    # overflow
+    extremes = [np.inf, 3.402823466e38, 1.1754944e-38, 1e-40, 1e30, 1e-30, np.nan, -1.0, -np.inf, -0.0,
+                1e-300, 1e-160]
     for k, v in enumerate(extremes):
         cells = rng.choice(F.size, size=200, replace=False)
         for c in cells:
