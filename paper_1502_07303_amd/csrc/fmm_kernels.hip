@@ -103,7 +103,7 @@ template <int E, typename FT, int G> struct TileLds {
     double T[Geo<E>::DV];                                // domain values (interior + face halos)
     FT F[Geo<E>::V];                                     // interior speeds (FP32), or h / F (FP64)
     uint16_t list[Geo<E>::V];                            // candidate list (interior indices)
-    alignas(8) uint8_t cf[BITS ? 8 : Geo<E>::V];         // byte flags
+    alignas(8) uint8_t cf[BITS ? 8 : Geo<E>::CFB];       // byte flags (+ per-lane spares)
     uint32_t cfw[BITS ? Geo<E>::V / 32 : 1];             // bit flags
     uint8_t fl[Geo<E>::DV];                              // FL_* per domain cell
     uint32_t stL[STAGE];                                 // staged live-list appends
@@ -253,16 +253,16 @@ __device__ __forceinline__ void stage_push(uint32_t *st, uint32_t &n, uint32_t v
     }
 }
 
-// Set candidate flag q if `on`.  Byte flags take a store under the lane
-// mask (lanes writing a shared spare byte instead all hit one LDS bank);
-// bit flags an LDS atomic OR.
+// Set candidate flag q if `on`.  Byte flags take one store from every lane:
+// a lane that does not mark writes its own spare dword (distinct banks), so
+// no lane mask has to be set up around the store; bit flags an LDS atomic OR.
 template <int E, typename FT, int G>
 __device__ __forceinline__ void mark_cand(TileLds<E, FT, G> &L, bool on, int q)
 {
     if constexpr (TileLds<E, FT, G>::BITS) {
         if (on) atomicOr(&L.cfw[q >> 5], 1u << (q & 31));
     } else {
-        if (on) L.cf[q] = 1;
+        L.cf[on ? q : Geo<E>::spare((int)__lane_id())] = 1;
     }
 }
 

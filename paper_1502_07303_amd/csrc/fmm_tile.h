@@ -21,6 +21,11 @@ template <int E> struct Geo {
     static constexpr int LOG = (E == 4) ? 2 : (E == 8) ? 3 : 4;
     __host__ __device__ static constexpr int dom(int i0, int i1, int i2) { return ((i0 + 1) * D + (i1 + 1)) * D + (i2 + 1); }
     __host__ __device__ static constexpr int domp(int p) { return dom(p >> (2 * LOG), (p >> LOG) & (E - 1), p & (E - 1)); }
+    // candidate bytes of a one-wavefront group: one per interior cell, then
+    // one spare dword per lane, which a lane that does not mark writes
+    // instead (so a mark is a store under no lane mask, in distinct banks)
+    static constexpr int CFB = V + 4 * 64;
+    __host__ __device__ static constexpr int spare(int lane) { return V + 4 * lane; }
 };
 
 

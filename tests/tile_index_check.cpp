@@ -107,6 +107,16 @@ template <int E> static void check_tile()
         // write-back of the axis-2 faces
         if (i2 == 0 || i2 == E - 1) CHECK(i0 * E + i1 < FACE);
     }
+    // the spare dwords of the candidate bytes: one per lane, past the
+    // interior flags (which alone the compaction reads), in distinct banks
+    {
+        std::set<int> banks;
+        for (int lane = 0; lane < 64; lane++) {
+            const int s = Gm::spare(lane);
+            CHECK(s >= V && s + 3 < Gm::CFB && s % 4 == 0);
+            if (lane < 32) CHECK(banks.insert((s / 4) % 32).second);
+        }
+    }
     // byte-flag compaction of a one-wavefront group: 64 lanes of K flags
     if (Gm::K % 8 == 0) {
         CHECK(64 * Gm::K == V);
